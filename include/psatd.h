@@ -1,0 +1,191 @@
+/*
+ * psatd.h -- C-ABI of libpsatd.so, the MI355X (gfx950) local-FFT PSATD field push.
+ *
+ * Method: H. Vincenti and J.-L. Vay, "Ultrahigh-order Maxwell solver with extreme
+ * scalability for electromagnetic PIC simulations of plasmas".
+ *   - Sec. 3.1, Eqs. PSATD_1 / PSATD_2: analytic k-space update of E and B over one
+ *     time step, with J at the half step held constant over the step;
+ *   - Sec. 3.1 (text after the equations): order-p modified wavenumbers
+ *     k_u -> sum_{j=1}^{p/2} w_j sin(j k_u du)/(du/2), p -> infinity = exact k;
+ *   - Sec. 3.2, Fig. 2a and Fig. 3: the global grid is cut into subdomains padded with
+ *     guard cells; each padded subdomain is advanced with its own local FFT as if it
+ *     were periodic, then its guard cells are replaced by the neighbours' values.
+ *
+ * One step, all on the device and in stream order:
+ *   exchange_J  -> forward local 3D FFT of E, B, J -> k-space update ->
+ *   inverse local 3D FFT of E, B -> exchange_EB.
+ *
+ * Units: d/dt B = -curl E, d/dt E = c^2 curl B - J (eps0 = 1, mu0 = 1/c^2); at c = 1
+ * this is the paper's normalisation.
+ *
+ * Conventions for every array argument below:
+ *   - 3-vectors of sizes are ordered (x, y, z);
+ *   - a "field buffer" is ONE device buffer per vector component (E[0..2] = Ex, Ey, Ez,
+ *     and likewise B and J).  It holds every subdomain's PADDED box back to back, in
+ *     subdomain order; box s starts at element offset(s) (see psatd_field_layout) and is
+ *     stored C-ordered [z][y][x] (x fastest) with extents n(s) + 2 guard(s).  The
+ *     element type is double for PSATD_F64 and float for every other precision.
+ *     Buffers must be 16-byte aligned (torch allocations are).
+ *   - a "global buffer" is one device buffer per component holding the interior grid,
+ *     C-ordered [z][y][x] with extents grid_n.
+ *
+ * Ownership: the caller owns every field, global and workspace buffer.  The plan owns
+ * its tables, kernels' launch configuration and captured graphs.  E and B are updated
+ * in place; J is read, and in PSATD_J_DEPOSITED mode its guard copies are overwritten by
+ * the summed currents.
+ *
+ * Errors: every call returns a psatd_status; no C++ exception crosses this interface and
+ * nothing here calls exit or abort.  The message of the last failure is available from
+ * psatd_last_error.  Work is enqueued asynchronously on the plan's stream, so a device
+ * fault surfaces at the next call that synchronises (psatd_sync).  A plan is not
+ * thread-safe; distinct plans are independent.
+ */
+#ifndef PSATD_H
+#define PSATD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct psatd_plan_s* psatd_plan_t;
+
+typedef enum {
+  PSATD_OK = 0,
+  PSATD_E_INVALID = 1,     /* bad argument: see psatd_last_error */
+  PSATD_E_NOMEM = 2,       /* device or host allocation failed */
+  PSATD_E_HIP = 3,         /* a HIP runtime call failed */
+  PSATD_E_UNSUPPORTED = 4, /* valid but not implemented (e.g. FFT length with a prime > 11) */
+  PSATD_E_STATE = 5        /* call not valid in the plan's current state */
+} psatd_status;
+
+typedef enum {
+  PSATD_F64 = 0,        /* FP64 state, FP64 FFT, FP64 update */
+  PSATD_F32_VALU = 1,   /* FP32 state and FFT (vector ALU), FP64 coefficients and update */
+  PSATD_F32_BF16X3 = 2, /* FP32 state, DFT stages as split-BF16 3-product MFMA GEMMs */
+  PSATD_F32_BF16X6 = 3  /* FP32 state, DFT stages as split-BF16 6-product MFMA GEMMs */
+} psatd_precision;
+
+typedef enum {
+  PSATD_J_REPLICATED = 0, /* every guard copy of J takes the owning subdomain's value */
+  PSATD_J_DEPOSITED = 1   /* J of a global cell = sum over all its padded copies, written to every copy */
+} psatd_jmode;
+
+/* Phases of one step, in execution order (for psatd_run_profiled). */
+enum {
+  PSATD_PHASE_EXCHANGE_J = 0,
+  PSATD_PHASE_FFT_XY_FWD = 1,  /* R2C along x + C2C along y, per z-plane, 9 fields */
+  PSATD_PHASE_Z_UPDATE = 2,    /* C2C along z, Eq. PSATD update, inverse C2C along z */
+  PSATD_PHASE_FFT_XY_INV = 3,  /* C2C along y + C2R along x, 6 fields, interior planes */
+  PSATD_PHASE_EXCHANGE_EB = 4,
+  PSATD_NPHASES = 5
+};
+
+/*
+ * psatd_plan -- build a plan (Sec. 3.2 decomposition, Sec. 3.1 operator).
+ *   grid_n[3]   global periodic interior cells (Nx, Ny, Nz), each >= 1
+ *   grid_d[3]   cell sizes (dx, dy, dz) > 0
+ *   nsub        number of subdomains >= 1
+ *   lo[nsub*3]  first owned global cell of each subdomain, (x, y, z)
+ *   n[nsub*3]   owned cells of each subdomain, (x, y, z); the boxes must tile the grid
+ *               exactly (no overlap, no gap)
+ *   guard[nsub*3] guard cells on each side, per subdomain and axis, >= 0; a guard may
+ *               exceed the neighbour's size or the grid (owners are found modulo N)
+ *   order_p     even >= 2 (finite-difference order of the modified wavenumber) or 0 for
+ *               infinite order (exact k)
+ *   dt          time step, any sign, nonzero and finite
+ *   c           speed of light > 0
+ *   precision   psatd_precision
+ *   jmode       psatd_jmode
+ *   stream      hipStream_t on which all work is enqueued (NULL = default stream)
+ * Padded lengths must have prime factors <= 11, the padded x length must be even, and
+ * one padded (y, x/2+1) complex plane must fit the 160 KiB LDS of a compute unit at the
+ * plan's precision; otherwise PSATD_E_UNSUPPORTED.  Uses the current HIP device.
+ * On success *out receives the plan; on failure *out is NULL.
+ */
+psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double grid_d[3],
+                        int32_t nsub, const int64_t* lo, const int64_t* n, const int32_t* guard,
+                        int32_t order_p, double dt, double c, int32_t precision, int32_t jmode,
+                        void* stream);
+
+/*
+ * psatd_validate -- the host-side checks of psatd_plan without touching the device.
+ * Same arguments (no stream).  On PSATD_OK, *field_elems (if not NULL) receives the
+ * number of elements of one field buffer.  Usable without a GPU.
+ */
+psatd_status psatd_validate(const int64_t grid_n[3], const double grid_d[3], int32_t nsub,
+                            const int64_t* lo, const int64_t* n, const int32_t* guard,
+                            int32_t order_p, double dt, double c, int32_t precision,
+                            int32_t jmode, int64_t* field_elems);
+
+/* Elements of one field buffer (= sum over subdomains of the padded volume). */
+psatd_status psatd_field_elems(psatd_plan_t plan, int64_t* total);
+
+/* Padded extents (x, y, z) of subdomain s and its element offset in a field buffer. */
+psatd_status psatd_field_layout(psatd_plan_t plan, int32_t s, int64_t padded_n[3],
+                                int64_t* offset_elems);
+
+/*
+ * Workspace: device scratch for the half-spectrum intermediates.  psatd_workspace_bytes
+ * gives the size; psatd_set_workspace hands the plan caller-owned device memory (at
+ * least that many bytes, 256-byte aligned; NULL/0 returns to plan-owned memory, which
+ * the plan allocates at the first step).  The caller keeps the memory alive while the
+ * plan uses it.
+ */
+psatd_status psatd_workspace_bytes(psatd_plan_t plan, int64_t* bytes);
+psatd_status psatd_set_workspace(psatd_plan_t plan, void* dev, int64_t bytes);
+
+/*
+ * psatd_step -- one step (exchange_J, local push of every padded box, exchange_EB),
+ * enqueued on the plan's stream.  E, B, J: arrays of 3 device field buffers.  The
+ * state must be consistent on entry (every guard copy equal to its owner, as
+ * psatd_scatter leaves it); it is consistent again on exit.
+ */
+psatd_status psatd_step(psatd_plan_t plan, void* const E[3], void* const B[3], void* const J[3]);
+
+/*
+ * psatd_run -- nsteps >= 0 steps with J unchanged, replayed from a captured HIP graph
+ * (captured once per (buffers, nsteps) and cached in the plan).
+ */
+psatd_status psatd_run(psatd_plan_t plan, void* const E[3], void* const B[3], void* const J[3],
+                       int32_t nsteps);
+
+/*
+ * psatd_run_profiled -- nsteps >= 1 steps launched directly with a HIP event pair
+ * around every phase; waits for completion and writes the mean milliseconds per step
+ * of each phase to phase_ms[PSATD_NPHASES] (host array).
+ */
+psatd_status psatd_run_profiled(psatd_plan_t plan, void* const E[3], void* const B[3],
+                                void* const J[3], int32_t nsteps, double* phase_ms);
+
+/*
+ * psatd_scatter -- global[3] (interior grid) -> padded[3] field buffers, guards filled
+ * from the owners (a consistent state).  psatd_gather -- padded interiors -> global[3].
+ */
+psatd_status psatd_scatter(psatd_plan_t plan, const void* const global[3], void* const padded[3]);
+psatd_status psatd_gather(psatd_plan_t plan, const void* const padded[3], void* const global[3]);
+
+/*
+ * psatd_modified_k -- copies the plan's FP64 modified-wavenumber table of axis u
+ * (0 = x, 1 = y, 2 = z) for subdomain s into host memory out[len] (len = padded length
+ * of that axis), over the FFT index m = 0..len-1 (Sec. 3.1).
+ */
+psatd_status psatd_modified_k(psatd_plan_t plan, int32_t s, int32_t axis, double* out,
+                              int64_t len);
+
+psatd_status psatd_set_stream(psatd_plan_t plan, void* stream);
+psatd_status psatd_sync(psatd_plan_t plan); /* waits for the plan's stream */
+void psatd_destroy(psatd_plan_t plan);       /* NULL-safe */
+
+const char* psatd_status_string(psatd_status st);
+/* Message of the last failure on this plan; plan == NULL gives the calling thread's last
+ * failure of psatd_plan / psatd_validate.  Never NULL. */
+const char* psatd_last_error(psatd_plan_t plan);
+/* Library version, "major.minor.patch". */
+const char* psatd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSATD_H */

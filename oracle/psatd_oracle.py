@@ -54,7 +54,10 @@ from functools import lru_cache
 import numpy as np
 import scipy.fft as sfft
 
-_WORKERS = os.cpu_count() or 1
+# FFT worker threads: the CPUs this process may use, at most 16 (override with
+# PSATD_ORACLE_WORKERS).
+_WORKERS = int(os.environ.get("PSATD_ORACLE_WORKERS",
+                              min(len(os.sched_getaffinity(0)) or 1, 16)))
 
 
 # --------------------------------------------------------------------------

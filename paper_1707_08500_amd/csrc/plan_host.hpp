@@ -1,0 +1,306 @@
+// Host-side planning of the local-FFT PSATD step (no HIP runtime calls):
+// validation of the decomposition (Sec. 3.2: boxes tiling the periodic grid,
+// guard cells per side), per-box padded extents, FFT radix schedules and their
+// twiddle / position tables, modified-wavenumber table layout (Sec. 3.1),
+// owner lookup, neighbour lists and the work lists of every phase.
+#pragma once
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "psatd.h"
+#include "psatd_device.hpp"
+
+namespace psatd {
+
+// ------------------------------------------------------------ host tables
+struct HostTables {
+  int64_t N[3];
+  double d[3];
+  int nsub;
+  int p;
+  double dt, c;
+  int prec, jmode;
+  std::vector<BoxD> box;
+  std::vector<FftPlanD> plans;
+  std::vector<long double> twr, twi;  // all twiddle tables, forward sign
+  std::vector<int32_t> idx;
+  std::vector<KEntry> kent;
+  int32_t kmod_len = 0;
+  int32_t kmax_len = 0;
+  std::vector<int32_t> cut[3];
+  int32_t ncut[3];
+  std::vector<int32_t> owner;
+  std::vector<int32_t> nbr_off, nbr;
+  std::vector<int32_t> itemsF, itemsU, itemsI, itemsP, itemsN;
+  int64_t field_elems = 0;
+  int64_t slab = 0;
+  int ldsF = 0, ldsI = 0, ldsU = 0, PB = 0, PPT = 0;
+};
+
+inline bool is_f64(int prec) { return prec == PSATD_F64; }
+inline size_t real_size(int prec) { return is_f64(prec) ? 8 : 4; }
+
+// radix schedule with the fewest stages (radices tried largest first)
+inline bool factorize(int N, std::vector<int>& out) {
+  static const int R[] = {16, 12, 11, 10, 8, 7, 6, 5, 4, 3, 2};
+  if (N == 1) { out.clear(); return true; }
+  for (int depth = 1; depth <= kMaxStages; ++depth) {
+    std::vector<int> cur;
+    // depth-first search for a factorisation of exactly `depth` radices
+    struct Rec {
+      static bool go(int n, int left, std::vector<int>& acc) {
+        if (left == 0) return n == 1;
+        for (int r : R) {
+          if (n % r) continue;
+          acc.push_back(r);
+          if (go(n / r, left - 1, acc)) return true;
+          acc.pop_back();
+        }
+        return false;
+      }
+    };
+    if (Rec::go(N, depth, cur)) { out = cur; return true; }
+  }
+  return false;
+}
+
+inline bool small_primes_only(int64_t n) {
+  for (int p : {2, 3, 5, 7, 11})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+// Adds (or finds) an FFT plan of length N; returns its index or -1.
+inline int add_plan(HostTables& h, int N) {
+  for (size_t i = 0; i < h.plans.size(); ++i)
+    if (h.plans[i].N == N) return (int)i;
+  std::vector<int> rad;
+  if (!factorize(N, rad)) return -1;
+  FftPlanD pl{};
+  pl.N = N;
+  pl.nstages = (int)rad.size();
+  for (int s = 0; s < kMaxStages; ++s) pl.radix[s] = s < pl.nstages ? rad[s] : 1;
+  pl.tw = (int32_t)h.twr.size();
+  const long double PI = 3.141592653589793238462643383279502884L;
+  for (int e = 0; e < N; ++e) {
+    h.twr.push_back(cosl(2.0L * PI * e / N));
+    h.twi.push_back(-sinl(2.0L * PI * e / N));
+  }
+  pl.pos = (int32_t)h.idx.size();
+  std::vector<int32_t> pos(N), ipos(N);
+  for (int k = 0; k < N; ++k) {
+    int64_t prod = 1, rem = k, p = 0, Nrem = N;
+    for (int s = 0; s < pl.nstages; ++s) {
+      const int t = (int)(rem % rad[s]);
+      rem /= rad[s];
+      Nrem /= rad[s];
+      p += (int64_t)t * Nrem;
+      prod *= rad[s];
+    }
+    pos[k] = (int32_t)p;
+  }
+  for (int k = 0; k < N; ++k) ipos[pos[k]] = k;
+  h.idx.insert(h.idx.end(), pos.begin(), pos.end());
+  pl.ipos = (int32_t)h.idx.size();
+  h.idx.insert(h.idx.end(), ipos.begin(), ipos.end());
+  h.plans.push_back(pl);
+  return (int)h.plans.size() - 1;
+}
+
+// twiddle table W_N^e without a plan (real <-> half spectrum, N = padded x)
+inline int add_twiddle(HostTables& h, int N, std::vector<std::pair<int, int>>& cache) {
+  for (auto& c : cache)
+    if (c.first == N) return c.second;
+  const int off = (int)h.twr.size();
+  const long double PI = 3.141592653589793238462643383279502884L;
+  for (int e = 0; e < N; ++e) {
+    h.twr.push_back(cosl(2.0L * PI * e / N));
+    h.twi.push_back(-sinl(2.0L * PI * e / N));
+  }
+  cache.push_back({N, off});
+  return off;
+}
+
+inline int add_kentry(HostTables& h, int N, double du) {
+  for (auto& k : h.kent)
+    if (k.N == N && k.du == du) return k.off;
+  KEntry k;
+  k.N = N;
+  k.du = du;
+  k.off = h.kmod_len;
+  h.kmod_len += N;
+  h.kmax_len = std::max(h.kmax_len, N);
+  h.kent.push_back(k);
+  return k.off;
+}
+
+// Does the circular interval [a, a+len) (len < N) meet [lo, lo+n) on Z_N?
+inline bool circ_meets(int64_t a, int64_t len, int64_t lo, int64_t n, int64_t N) {
+  if (len >= N) return true;
+  for (int k = -2; k <= 2; ++k) {
+    const int64_t s = a + k * N, e = s + len;
+    if (s < lo + n && lo < e) return true;
+  }
+  return false;
+}
+
+inline psatd_status build_host(HostTables& h, std::string& err, const int64_t grid_n[3],
+                        const double grid_d[3], int32_t nsub, const int64_t* lo, const int64_t* n,
+                        const int32_t* guard, int32_t order_p, double dt, double c,
+                        int32_t precision, int32_t jmode) {
+  auto bad = [&](psatd_status st, const std::string& m) {
+    err = m;
+    return st;
+  };
+  if (!grid_n || !grid_d || !lo || !n || !guard) return bad(PSATD_E_INVALID, "null pointer argument");
+  if (nsub < 1) return bad(PSATD_E_INVALID, "nsub must be >= 1");
+  for (int u = 0; u < 3; ++u) {
+    if (grid_n[u] < 1 || grid_n[u] > (1 << 24)) return bad(PSATD_E_INVALID, "grid_n out of range");
+    if (!(grid_d[u] > 0.0) || !std::isfinite(grid_d[u])) return bad(PSATD_E_INVALID, "grid_d must be finite and > 0");
+  }
+  if (order_p < 0 || (order_p % 2) != 0 || order_p == 1)
+    return bad(PSATD_E_INVALID, "order_p must be 0 (infinite) or even >= 2");
+  if (!(dt != 0.0) || !std::isfinite(dt)) return bad(PSATD_E_INVALID, "dt must be finite and nonzero");
+  if (!(c > 0.0) || !std::isfinite(c)) return bad(PSATD_E_INVALID, "c must be finite and > 0");
+  if (precision < PSATD_F64 || precision > PSATD_F32_BF16X6) return bad(PSATD_E_INVALID, "unknown precision");
+  if (precision == PSATD_F32_BF16X3 || precision == PSATD_F32_BF16X6)
+    return bad(PSATD_E_UNSUPPORTED, "split-BF16 MFMA DFT stages are not built in this library version");
+  if (jmode != PSATD_J_REPLICATED && jmode != PSATD_J_DEPOSITED) return bad(PSATD_E_INVALID, "unknown jmode");
+
+  for (int u = 0; u < 3; ++u) {
+    h.N[u] = grid_n[u];
+    h.d[u] = grid_d[u];
+  }
+  h.nsub = nsub;
+  h.p = order_p;
+  h.dt = dt;
+  h.c = c;
+  h.prec = precision;
+  h.jmode = jmode;
+
+  // boxes inside the grid, guards >= 0
+  for (int s = 0; s < nsub; ++s)
+    for (int u = 0; u < 3; ++u) {
+      const int64_t l = lo[3 * s + u], m = n[3 * s + u];
+      if (m < 1 || l < 0 || l + m > grid_n[u]) return bad(PSATD_E_INVALID, "box " + std::to_string(s) + " outside the grid");
+      if (guard[3 * s + u] < 0) return bad(PSATD_E_INVALID, "negative guard width");
+      if (m + 2 * (int64_t)guard[3 * s + u] > (1 << 20)) return bad(PSATD_E_INVALID, "padded length too large");
+    }
+  // refined cuts and owner table: exact tiling
+  for (int u = 0; u < 3; ++u) {
+    std::vector<int64_t> pts{0, grid_n[u]};
+    for (int s = 0; s < nsub; ++s) {
+      pts.push_back(lo[3 * s + u]);
+      pts.push_back(lo[3 * s + u] + n[3 * s + u]);
+    }
+    std::sort(pts.begin(), pts.end());
+    pts.erase(std::unique(pts.begin(), pts.end()), pts.end());
+    h.ncut[u] = (int32_t)pts.size() - 1;
+    h.cut[u].assign(grid_n[u], 0);
+    for (int i = 0; i < h.ncut[u]; ++i)
+      for (int64_t x = pts[i]; x < pts[i + 1]; ++x) h.cut[u][x] = i;
+  }
+  const int64_t ncell = (int64_t)h.ncut[0] * h.ncut[1] * h.ncut[2];
+  if (ncell > (int64_t)1 << 26) return bad(PSATD_E_UNSUPPORTED, "decomposition too fine");
+  h.owner.assign(ncell, -1);
+  for (int s = 0; s < nsub; ++s) {
+    int c0[3], c1[3];
+    for (int u = 0; u < 3; ++u) {
+      c0[u] = h.cut[u][lo[3 * s + u]];
+      c1[u] = h.cut[u][lo[3 * s + u] + n[3 * s + u] - 1] + 1;
+    }
+    for (int cz = c0[2]; cz < c1[2]; ++cz)
+      for (int cy = c0[1]; cy < c1[1]; ++cy)
+        for (int cx = c0[0]; cx < c1[0]; ++cx) {
+          int32_t& o = h.owner[((int64_t)cz * h.ncut[1] + cy) * h.ncut[0] + cx];
+          if (o != -1) return bad(PSATD_E_INVALID, "boxes " + std::to_string(o) + " and " + std::to_string(s) + " overlap");
+          o = s;
+        }
+  }
+  for (int32_t o : h.owner)
+    if (o < 0) return bad(PSATD_E_INVALID, "boxes leave part of the grid uncovered");
+
+  // per box: padded extents, FFT plans, tables, offsets
+  const bool f64 = is_f64(precision);
+  const int csz = (int)(2 * real_size(precision));
+  std::vector<std::pair<int, int>> twcache;
+  h.box.resize(nsub);
+  int64_t foff = 0, soff = 0;
+  int maxPz = 0;
+  for (int s = 0; s < nsub; ++s) {
+    BoxD& b = h.box[s];
+    std::memset(&b, 0, sizeof(b));
+    for (int u = 0; u < 3; ++u) {
+      b.lo[u] = (int32_t)lo[3 * s + u];
+      b.n[u] = (int32_t)n[3 * s + u];
+      b.g[u] = guard[3 * s + u];
+      b.P[u] = b.n[u] + 2 * b.g[u];
+      if (!small_primes_only(b.P[u]))
+        return bad(PSATD_E_UNSUPPORTED, "padded length " + std::to_string(b.P[u]) + " has a prime factor > 11");
+    }
+    if (b.P[0] % 2) return bad(PSATD_E_UNSUPPORTED, "padded x length must be even");
+    b.H = b.P[0] / 2 + 1;
+    b.ld = (b.H % 2) ? b.H : b.H + 1;
+    b.planx = add_plan(h, b.P[0] / 2);
+    b.plany = add_plan(h, b.P[1]);
+    b.planz = add_plan(h, b.P[2]);
+    if (b.planx < 0 || b.plany < 0 || b.planz < 0)
+      return bad(PSATD_E_UNSUPPORTED, "no radix schedule of <= 4 stages for a padded length");
+    b.twr = add_twiddle(h, b.P[0], twcache);
+    b.kx = add_kentry(h, b.P[0], grid_d[0]);
+    b.ky = add_kentry(h, b.P[1], grid_d[1]);
+    b.kz = add_kentry(h, b.P[2], grid_d[2]);
+    b.foff = foff;
+    b.soff = soff;
+    foff += (int64_t)b.P[0] * b.P[1] * b.P[2];
+    soff += (int64_t)b.H * b.P[1] * b.P[2];
+    h.ldsF = std::max<int>(h.ldsF, b.P[1] * b.ld * csz);
+    h.ldsI = h.ldsF;
+    maxPz = std::max(maxPz, b.P[2]);
+  }
+  if (h.twr.size() > (size_t)INT32_MAX / 2 || h.idx.size() > (size_t)INT32_MAX / 2)
+    return bad(PSATD_E_UNSUPPORTED, "tables too large");
+  h.field_elems = foff;
+  h.slab = soff;
+  if (h.ldsF > kMaxDynLds)
+    return bad(PSATD_E_UNSUPPORTED, "a padded (y, x/2+1) plane exceeds the 160 KiB LDS at this precision");
+  h.PB = f64 ? kPB64 : kPB32;
+  const int NT = f64 ? kThreadsU64 : kThreadsU32;
+  h.PPT = (maxPz * h.PB + NT - 1) / NT;
+  if (h.PPT > kMaxPPT) return bad(PSATD_E_UNSUPPORTED, "padded z length too large for the z-update kernel");
+  h.ldsU = maxPz * h.PB * csz;
+
+  // neighbours: boxes whose padded region meets the interior of s (for the
+  // deposited-current sum), ascending
+  h.nbr_off.assign(nsub + 1, 0);
+  h.nbr.clear();
+  if (jmode == PSATD_J_DEPOSITED) {
+    for (int s = 0; s < nsub; ++s) {
+      for (int s2 = 0; s2 < nsub; ++s2) {
+        bool meets = true;
+        for (int u = 0; u < 3 && meets; ++u)
+          meets = circ_meets((int64_t)h.box[s2].lo[u] - h.box[s2].g[u], h.box[s2].P[u], h.box[s].lo[u],
+                             h.box[s].n[u], grid_n[u]);
+        if (meets) h.nbr.push_back(s2);
+      }
+      h.nbr_off[s + 1] = (int32_t)h.nbr.size();
+    }
+  }
+  // work lists
+  auto prefix = [&](std::vector<int32_t>& v, auto count) {
+    v.assign(nsub + 1, 0);
+    for (int s = 0; s < nsub; ++s) v[s + 1] = v[s] + (int32_t)count(h.box[s]);
+  };
+  const int PB = h.PB;
+  prefix(h.itemsF, [](const BoxD& b) { return (int64_t)b.P[2] * 9; });
+  prefix(h.itemsU, [PB](const BoxD& b) { return ((int64_t)b.P[1] * b.H + PB - 1) / PB; });
+  prefix(h.itemsI, [](const BoxD& b) { return (int64_t)b.n[2] * 6; });
+  prefix(h.itemsP, [](const BoxD& b) { return (int64_t)b.P[2]; });
+  prefix(h.itemsN, [](const BoxD& b) { return (int64_t)b.n[2]; });
+  return PSATD_OK;
+}
+
+}  // namespace psatd

@@ -1,0 +1,476 @@
+// Host side of libpsatd.so: plan construction (Sec. 3.2 decomposition, Sec. 3.1
+// operator), validation, device tables, step enqueue, graph capture and the
+// C-ABI declared in include/psatd.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "psatd.h"
+#include "plan_host.hpp"
+#include "psatd_launch.hpp"
+
+using namespace psatd;
+
+namespace {
+
+thread_local std::string g_last_error = "";
+
+struct GraphEntry {
+  void* ptr[9];
+  int32_t nsteps;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------- the plan
+struct psatd_plan_s {
+  HostTables h;
+  DevPlan dp;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  int device = 0;
+  void* blob = nullptr;  // device tables
+  void* ws = nullptr;
+  int64_t ws_bytes = 0;
+  bool ws_owned = false;
+  std::vector<GraphEntry> graphs;
+  std::string err;
+};
+
+namespace {
+
+psatd_status fail(psatd_plan_t p, psatd_status st, const std::string& m) {
+  if (p) p->err = m; else g_last_error = m;
+  return st;
+}
+
+#define HIPCHK(plan, call)                                                                    \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail(plan, e_ == hipErrorOutOfMemory ? PSATD_E_NOMEM : PSATD_E_HIP,              \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                         \
+  } while (0)
+
+int64_t workspace_need(const psatd_plan_s* p) {
+  return 9 * p->h.slab * (int64_t)(2 * real_size(p->h.prec));
+}
+
+void drop_graphs(psatd_plan_t p) {
+  for (auto& g : p->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  p->graphs.clear();
+}
+
+psatd_status ensure_workspace(psatd_plan_t p) {
+  if (p->ws) return PSATD_OK;
+  const int64_t need = workspace_need(p);
+  HIPCHK(p, hipMalloc(&p->ws, (size_t)std::max<int64_t>(need, 256)));
+  p->ws_bytes = need;
+  p->ws_owned = true;
+  return PSATD_OK;
+}
+
+bool aligned16(const void* q) { return ((uintptr_t)q & 15u) == 0; }
+
+psatd_status check_fields(psatd_plan_t p, void* const* v, int count, const char* what) {
+  if (!v) return fail(p, PSATD_E_INVALID, std::string(what) + ": null array");
+  for (int i = 0; i < count; ++i) {
+    if (!v[i]) return fail(p, PSATD_E_INVALID, std::string(what) + ": null buffer");
+    if (!aligned16(v[i])) return fail(p, PSATD_E_INVALID, std::string(what) + ": buffer not 16-byte aligned");
+  }
+  return PSATD_OK;
+}
+
+psatd_status enqueue_phase(psatd_plan_t p, int ph, void* const E[3], void* const B[3], void* const J[3],
+                           hipStream_t st) {
+  const DevPlan& d = p->dp;
+  void* eb[6] = {E[0], E[1], E[2], B[0], B[1], B[2]};
+  switch (ph) {
+    case kPhaseExchJ:
+      if (p->h.jmode == PSATD_J_DEPOSITED) HIPCHK(p, launch_sum(d, J, st));
+      HIPCHK(p, launch_fill(d, J, 3, st));
+      break;
+    case kPhaseFwd: {
+      void* in9[9] = {E[0], E[1], E[2], B[0], B[1], B[2], J[0], J[1], J[2]};
+      HIPCHK(p, launch_fwd(d, in9, p->ws, st));
+      break;
+    }
+    case kPhaseUpd:
+      HIPCHK(p, launch_upd(d, p->ws, st));
+      break;
+    case kPhaseInv:
+      HIPCHK(p, launch_inv(d, p->ws, eb, st));
+      break;
+    case kPhaseExchEB:
+      HIPCHK(p, launch_fill(d, eb, 6, st));
+      break;
+  }
+  return PSATD_OK;
+}
+
+psatd_status enqueue_step(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3],
+                          hipStream_t st) {
+  for (int ph = 0; ph < kNumPhases; ++ph) {
+    psatd_status r = enqueue_phase(p, ph, E, B, J, st);
+    if (r != PSATD_OK) return r;
+  }
+  return PSATD_OK;
+}
+
+psatd_status check_step_args(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3]) {
+  if (!p) return fail(nullptr, PSATD_E_INVALID, "null plan");
+  psatd_status r;
+  if ((r = check_fields(p, E, 3, "E")) != PSATD_OK) return r;
+  if ((r = check_fields(p, B, 3, "B")) != PSATD_OK) return r;
+  if ((r = check_fields(p, J, 3, "J")) != PSATD_OK) return r;
+  return ensure_workspace(p);
+}
+
+}  // namespace
+
+extern "C" {
+
+psatd_status psatd_validate(const int64_t grid_n[3], const double grid_d[3], int32_t nsub,
+                            const int64_t* lo, const int64_t* n, const int32_t* guard,
+                            int32_t order_p, double dt, double c, int32_t precision,
+                            int32_t jmode, int64_t* field_elems) {
+  try {
+    HostTables h;
+    std::string err;
+    psatd_status st = build_host(h, err, grid_n, grid_d, nsub, lo, n, guard, order_p, dt, c,
+                                 precision, jmode);
+    if (st != PSATD_OK) return fail(nullptr, st, err);
+    if (field_elems) *field_elems = h.field_elems;
+    return PSATD_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(nullptr, PSATD_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(nullptr, PSATD_E_INVALID, "unexpected host exception");
+  }
+}
+
+psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double grid_d[3],
+                        int32_t nsub, const int64_t* lo, const int64_t* n, const int32_t* guard,
+                        int32_t order_p, double dt, double c, int32_t precision, int32_t jmode,
+                        void* stream) {
+  if (!out) return fail(nullptr, PSATD_E_INVALID, "null output pointer");
+  *out = nullptr;
+  psatd_plan_s* p = nullptr;
+  try {
+    p = new psatd_plan_s();
+  } catch (...) {
+    return fail(nullptr, PSATD_E_NOMEM, "host allocation failed");
+  }
+  psatd_status st;
+  try {
+    std::string err;
+    st = build_host(p->h, err, grid_n, grid_d, nsub, lo, n, guard, order_p, dt, c, precision, jmode);
+    if (st != PSATD_OK) {
+      delete p;
+      return fail(nullptr, st, err);
+    }
+  } catch (...) {
+    delete p;
+    return fail(nullptr, PSATD_E_NOMEM, "host allocation failed");
+  }
+  HostTables& h = p->h;
+  p->stream = reinterpret_cast<hipStream_t>(stream);
+  auto hipfail = [&](hipError_t e, const char* what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    psatd_destroy(p);
+    return fail(nullptr, e == hipErrorOutOfMemory ? PSATD_E_NOMEM : PSATD_E_HIP, m);
+  };
+  hipError_t e;
+  if ((e = hipGetDevice(&p->device)) != hipSuccess) return hipfail(e, "hipGetDevice");
+  if ((e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+    return hipfail(e, "hipStreamCreateWithFlags");
+
+  // one device blob for every table
+  const bool f64 = is_f64(h.prec);
+  const size_t cs = 2 * real_size(h.prec);
+  std::vector<std::pair<size_t, size_t>> parts;  // (offset, bytes)
+  size_t total = 0;
+  auto reserve = [&](size_t bytes) {
+    const size_t off = total;
+    total += (bytes + 255) & ~(size_t)255;
+    return off;
+  };
+  const size_t o_box = reserve(h.box.size() * sizeof(BoxD));
+  const size_t o_plan = reserve(h.plans.size() * sizeof(FftPlanD));
+  const size_t o_tw = reserve(h.twr.size() * cs);
+  const size_t o_idx = reserve(h.idx.size() * 4);
+  const size_t o_kmod = reserve((size_t)h.kmod_len * 8);
+  const size_t o_kent = reserve(h.kent.size() * sizeof(KEntry));
+  size_t o_cut[3];
+  for (int u = 0; u < 3; ++u) o_cut[u] = reserve(h.cut[u].size() * 4);
+  const size_t o_own = reserve(h.owner.size() * 4);
+  const size_t o_nbo = reserve(h.nbr_off.size() * 4);
+  const size_t o_nbr = reserve(std::max<size_t>(h.nbr.size(), 1) * 4);
+  const size_t o_iF = reserve(h.itemsF.size() * 4);
+  const size_t o_iU = reserve(h.itemsU.size() * 4);
+  const size_t o_iI = reserve(h.itemsI.size() * 4);
+  const size_t o_iP = reserve(h.itemsP.size() * 4);
+  const size_t o_iN = reserve(h.itemsN.size() * 4);
+  std::vector<unsigned char> hb(total, 0);
+  auto put = [&](size_t off, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(hb.data() + off, src, bytes);
+  };
+  put(o_box, h.box.data(), h.box.size() * sizeof(BoxD));
+  put(o_plan, h.plans.data(), h.plans.size() * sizeof(FftPlanD));
+  if (f64) {
+    std::vector<cx<double>> t(h.twr.size());
+    for (size_t i = 0; i < t.size(); ++i) t[i] = {(double)h.twr[i], (double)h.twi[i]};
+    put(o_tw, t.data(), t.size() * sizeof(cx<double>));
+  } else {
+    std::vector<cx<float>> t(h.twr.size());
+    for (size_t i = 0; i < t.size(); ++i) t[i] = {(float)h.twr[i], (float)h.twi[i]};
+    put(o_tw, t.data(), t.size() * sizeof(cx<float>));
+  }
+  put(o_idx, h.idx.data(), h.idx.size() * 4);
+  put(o_kent, h.kent.data(), h.kent.size() * sizeof(KEntry));
+  for (int u = 0; u < 3; ++u) put(o_cut[u], h.cut[u].data(), h.cut[u].size() * 4);
+  put(o_own, h.owner.data(), h.owner.size() * 4);
+  put(o_nbo, h.nbr_off.data(), h.nbr_off.size() * 4);
+  put(o_nbr, h.nbr.data(), h.nbr.size() * 4);
+  put(o_iF, h.itemsF.data(), h.itemsF.size() * 4);
+  put(o_iU, h.itemsU.data(), h.itemsU.size() * 4);
+  put(o_iI, h.itemsI.data(), h.itemsI.size() * 4);
+  put(o_iP, h.itemsP.data(), h.itemsP.size() * 4);
+  put(o_iN, h.itemsN.data(), h.itemsN.size() * 4);
+  if ((e = hipMalloc(&p->blob, total)) != hipSuccess) return hipfail(e, "hipMalloc(tables)");
+  if ((e = hipMemcpy(p->blob, hb.data(), total, hipMemcpyHostToDevice)) != hipSuccess)
+    return hipfail(e, "hipMemcpy(tables)");
+  unsigned char* B = reinterpret_cast<unsigned char*>(p->blob);
+  // (a1) modified wavenumbers, FP64, on the device
+  if ((e = launch_modk(reinterpret_cast<const KEntry*>(B + o_kent), (int)h.kent.size(), h.kmax_len, h.p,
+                       reinterpret_cast<double*>(B + o_kmod), p->cap_stream)) != hipSuccess)
+    return hipfail(e, "modified-wavenumber kernel");
+  if ((e = hipStreamSynchronize(p->cap_stream)) != hipSuccess) return hipfail(e, "modified-wavenumber kernel");
+  if ((e = prepare_kernels(f64, h.ldsF, h.ldsI, h.ldsU, h.PPT)) != hipSuccess)
+    return hipfail(e, "hipFuncSetAttribute");
+
+  DevPlan& d = p->dp;
+  std::memset(&d, 0, sizeof(d));
+  d.f64 = f64;
+  d.nsub = h.nsub;
+  for (int u = 0; u < 3; ++u) d.N[u] = (int32_t)h.N[u];
+  d.box = reinterpret_cast<const BoxD*>(B + o_box);
+  d.plans = reinterpret_cast<const FftPlanD*>(B + o_plan);
+  d.tw = B + o_tw;
+  d.idx = reinterpret_cast<const int32_t*>(B + o_idx);
+  d.kmod = reinterpret_cast<const double*>(B + o_kmod);
+  for (int u = 0; u < 3; ++u) {
+    d.own.cut[u] = reinterpret_cast<const int32_t*>(B + o_cut[u]);
+    d.own.ncut[u] = h.ncut[u];
+    d.own.N[u] = (int32_t)h.N[u];
+  }
+  d.own.owner = reinterpret_cast<const int32_t*>(B + o_own);
+  d.nbr_off = reinterpret_cast<const int32_t*>(B + o_nbo);
+  d.nbr = reinterpret_cast<const int32_t*>(B + o_nbr);
+  d.itemsF = reinterpret_cast<const int32_t*>(B + o_iF);
+  d.itemsU = reinterpret_cast<const int32_t*>(B + o_iU);
+  d.itemsI = reinterpret_cast<const int32_t*>(B + o_iI);
+  d.itemsP = reinterpret_cast<const int32_t*>(B + o_iP);
+  d.itemsN = reinterpret_cast<const int32_t*>(B + o_iN);
+  d.nF = h.itemsF.back();
+  d.nU = h.itemsU.back();
+  d.nI = h.itemsI.back();
+  d.nP = h.itemsP.back();
+  d.nN = h.itemsN.back();
+  d.ldsF = h.ldsF;
+  d.ldsI = h.ldsI;
+  d.ldsU = h.ldsU;
+  d.PB = h.PB;
+  d.PPT = h.PPT;
+  d.slab = h.slab;
+  d.c = h.c;
+  d.dt = h.dt;
+  *out = p;
+  return PSATD_OK;
+}
+
+void psatd_destroy(psatd_plan_t p) {
+  if (!p) return;
+  drop_graphs(p);
+  if (p->ws_owned && p->ws) (void)hipFree(p->ws);
+  if (p->blob) (void)hipFree(p->blob);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  delete p;
+}
+
+psatd_status psatd_field_elems(psatd_plan_t p, int64_t* total) {
+  if (!p || !total) return fail(p, PSATD_E_INVALID, "null argument");
+  *total = p->h.field_elems;
+  return PSATD_OK;
+}
+
+psatd_status psatd_field_layout(psatd_plan_t p, int32_t s, int64_t padded_n[3], int64_t* offset) {
+  if (!p || !padded_n || !offset) return fail(p, PSATD_E_INVALID, "null argument");
+  if (s < 0 || s >= p->h.nsub) return fail(p, PSATD_E_INVALID, "subdomain index out of range");
+  const BoxD& b = p->h.box[s];
+  for (int u = 0; u < 3; ++u) padded_n[u] = b.P[u];
+  *offset = b.foff;
+  return PSATD_OK;
+}
+
+psatd_status psatd_workspace_bytes(psatd_plan_t p, int64_t* bytes) {
+  if (!p || !bytes) return fail(p, PSATD_E_INVALID, "null argument");
+  *bytes = workspace_need(p);
+  return PSATD_OK;
+}
+
+psatd_status psatd_set_workspace(psatd_plan_t p, void* dev, int64_t bytes) {
+  if (!p) return fail(p, PSATD_E_INVALID, "null plan");
+  if (dev && bytes < workspace_need(p)) return fail(p, PSATD_E_INVALID, "workspace too small");
+  if (dev && ((uintptr_t)dev & 255u)) return fail(p, PSATD_E_INVALID, "workspace not 256-byte aligned");
+  drop_graphs(p);
+  if (p->ws_owned && p->ws) HIPCHK(p, hipFree(p->ws));
+  p->ws = dev;
+  p->ws_bytes = dev ? bytes : 0;
+  p->ws_owned = false;
+  return PSATD_OK;
+}
+
+psatd_status psatd_step(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3]) {
+  psatd_status r = check_step_args(p, E, B, J);
+  if (r != PSATD_OK) return r;
+  return enqueue_step(p, E, B, J, p->stream);
+}
+
+psatd_status psatd_run(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3],
+                       int32_t nsteps) {
+  psatd_status r = check_step_args(p, E, B, J);
+  if (r != PSATD_OK) return r;
+  if (nsteps < 0) return fail(p, PSATD_E_INVALID, "nsteps < 0");
+  if (nsteps == 0) return PSATD_OK;
+  void* key[9] = {E[0], E[1], E[2], B[0], B[1], B[2], J[0], J[1], J[2]};
+  GraphEntry* ge = nullptr;
+  for (auto& g : p->graphs)
+    if (g.nsteps == nsteps && std::memcmp(g.ptr, key, sizeof(key)) == 0) ge = &g;
+  if (!ge) {
+    if (p->graphs.size() >= 8) drop_graphs(p);
+    GraphEntry g{};
+    std::memcpy(g.ptr, key, sizeof(key));
+    g.nsteps = nsteps;
+    HIPCHK(p, hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed));
+    psatd_status er = PSATD_OK;
+    for (int i = 0; i < nsteps && er == PSATD_OK; ++i) er = enqueue_step(p, E, B, J, p->cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
+    if (er != PSATD_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return er;
+    }
+    if (e2 != hipSuccess) return fail(p, PSATD_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
+    g.graph = graph;
+    hipError_t e3 = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    if (e3 != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return fail(p, PSATD_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e3));
+    }
+    p->graphs.push_back(g);
+    ge = &p->graphs.back();
+  }
+  HIPCHK(p, hipGraphLaunch(ge->exec, p->stream));
+  return PSATD_OK;
+}
+
+psatd_status psatd_run_profiled(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3],
+                                int32_t nsteps, double* phase_ms) {
+  psatd_status r = check_step_args(p, E, B, J);
+  if (r != PSATD_OK) return r;
+  if (nsteps < 1 || !phase_ms) return fail(p, PSATD_E_INVALID, "nsteps < 1 or null phase_ms");
+  hipEvent_t ev[kNumPhases + 1];
+  for (int i = 0; i <= kNumPhases; ++i) HIPCHK(p, hipEventCreate(&ev[i]));
+  double acc[kNumPhases] = {0, 0, 0, 0, 0};
+  psatd_status out = PSATD_OK;
+  for (int st = 0; st < nsteps && out == PSATD_OK; ++st) {
+    for (int ph = 0; ph < kNumPhases && out == PSATD_OK; ++ph) {
+      hipError_t e = hipEventRecord(ev[ph], p->stream);
+      if (e != hipSuccess) { out = fail(p, PSATD_E_HIP, "hipEventRecord"); break; }
+      out = enqueue_phase(p, ph, E, B, J, p->stream);
+    }
+    if (out != PSATD_OK) break;
+    if (hipEventRecord(ev[kNumPhases], p->stream) != hipSuccess) { out = fail(p, PSATD_E_HIP, "hipEventRecord"); break; }
+    if (hipEventSynchronize(ev[kNumPhases]) != hipSuccess) { out = fail(p, PSATD_E_HIP, "hipEventSynchronize"); break; }
+    for (int ph = 0; ph < kNumPhases; ++ph) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[ph], ev[ph + 1]) != hipSuccess) { out = fail(p, PSATD_E_HIP, "hipEventElapsedTime"); break; }
+      acc[ph] += ms;
+    }
+  }
+  for (int i = 0; i <= kNumPhases; ++i) (void)hipEventDestroy(ev[i]);
+  if (out != PSATD_OK) return out;
+  for (int ph = 0; ph < kNumPhases; ++ph) phase_ms[ph] = acc[ph] / nsteps;
+  return PSATD_OK;
+}
+
+psatd_status psatd_scatter(psatd_plan_t p, const void* const global[3], void* const padded[3]) {
+  if (!p) return fail(nullptr, PSATD_E_INVALID, "null plan");
+  psatd_status r;
+  if ((r = check_fields(p, const_cast<void* const*>(global), 3, "global")) != PSATD_OK) return r;
+  if ((r = check_fields(p, padded, 3, "padded")) != PSATD_OK) return r;
+  HIPCHK(p, launch_scatter(p->dp, global, padded, p->stream));
+  return PSATD_OK;
+}
+
+psatd_status psatd_gather(psatd_plan_t p, const void* const padded[3], void* const global[3]) {
+  if (!p) return fail(nullptr, PSATD_E_INVALID, "null plan");
+  psatd_status r;
+  if ((r = check_fields(p, const_cast<void* const*>(padded), 3, "padded")) != PSATD_OK) return r;
+  if ((r = check_fields(p, global, 3, "global")) != PSATD_OK) return r;
+  HIPCHK(p, launch_gather(p->dp, padded, global, p->stream));
+  return PSATD_OK;
+}
+
+psatd_status psatd_modified_k(psatd_plan_t p, int32_t s, int32_t axis, double* out, int64_t len) {
+  if (!p || !out) return fail(p, PSATD_E_INVALID, "null argument");
+  if (s < 0 || s >= p->h.nsub || axis < 0 || axis > 2) return fail(p, PSATD_E_INVALID, "index out of range");
+  const BoxD& b = p->h.box[s];
+  if (len != b.P[axis]) return fail(p, PSATD_E_INVALID, "len must equal the padded length of the axis");
+  const int off = axis == 0 ? b.kx : (axis == 1 ? b.ky : b.kz);
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  HIPCHK(p, hipMemcpy(out, p->dp.kmod + off, (size_t)len * 8, hipMemcpyDeviceToHost));
+  return PSATD_OK;
+}
+
+psatd_status psatd_set_stream(psatd_plan_t p, void* stream) {
+  if (!p) return fail(nullptr, PSATD_E_INVALID, "null plan");
+  p->stream = reinterpret_cast<hipStream_t>(stream);
+  return PSATD_OK;
+}
+
+psatd_status psatd_sync(psatd_plan_t p) {
+  if (!p) return fail(nullptr, PSATD_E_INVALID, "null plan");
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  return PSATD_OK;
+}
+
+const char* psatd_status_string(psatd_status st) {
+  switch (st) {
+    case PSATD_OK: return "PSATD_OK";
+    case PSATD_E_INVALID: return "PSATD_E_INVALID";
+    case PSATD_E_NOMEM: return "PSATD_E_NOMEM";
+    case PSATD_E_HIP: return "PSATD_E_HIP";
+    case PSATD_E_UNSUPPORTED: return "PSATD_E_UNSUPPORTED";
+    case PSATD_E_STATE: return "PSATD_E_STATE";
+  }
+  return "PSATD_E_UNKNOWN";
+}
+
+const char* psatd_last_error(psatd_plan_t p) { return p ? p->err.c_str() : g_last_error.c_str(); }
+
+const char* psatd_version(void) { return "0.1.0"; }
+
+}  // extern "C"

@@ -1,0 +1,267 @@
+// __global__ wrappers and launchers for the phases of the local-FFT PSATD step.
+//
+// Every phase is ONE launch over a flattened work list spanning all subdomains
+// (uneven sizes and guard widths included): a work-group takes items
+// blockIdx.x, blockIdx.x + gridDim.x, ... so the same kernel runs either one
+// work-group per item or as a persistent grid.
+#include <hip/hip_runtime.h>
+
+#include "psatd_launch.hpp"
+
+namespace psatd {
+
+struct BlockBarrier {
+  __device__ void operator()() const { __syncthreads(); }
+};
+
+extern __shared__ __attribute__((aligned(16))) unsigned char psatd_lds[];
+
+template <typename T>
+__global__ __launch_bounds__(kThreadsXY) void k_fwd_xy(FwdArgs<T> a, int nitems) {
+  cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    body_fwd_xy(a, item, threadIdx.x, blockDim.x, lds, BlockBarrier{});
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreadsXY) void k_inv_xy(InvArgs<T> a, int nitems) {
+  cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    body_inv_xy(a, item, threadIdx.x, blockDim.x, lds, BlockBarrier{});
+    __syncthreads();
+  }
+}
+
+template <typename T, int NT, int PB, int PPT>
+__global__ __launch_bounds__(NT) void k_z_update(UpdArgs<T> a, int nitems) {
+  cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    body_z_update<T, PB, PPT>(a, item, threadIdx.x, NT, lds, BlockBarrier{});
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreadsXY) void k_fill(FillArgs<T> a, int nitems) {
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x)
+    body_fill(a, item, threadIdx.x, blockDim.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreadsXY) void k_sum(SumArgs<T> a, int nitems) {
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x)
+    body_sum(a, item, threadIdx.x, blockDim.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreadsXY) void k_scatter(ScatterArgs<T> a, int nitems) {
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x)
+    body_scatter(a, item, threadIdx.x, blockDim.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreadsXY) void k_gather(ScatterArgs<T> a, int nitems) {
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x)
+    body_gather(a, item, threadIdx.x, blockDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_modk(const KEntry* ent, int nent, int maxN, int p,
+                                              double* kmod) {
+  const int e = blockIdx.y;
+  if (e >= nent) return;
+  const KEntry k = ent[e];
+  for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < k.N; m += gridDim.x * blockDim.x)
+    kmod[k.off + m] = modified_k_entry(k.N, k.du, p, m);
+}
+
+// ------------------------------------------------------------------ helpers
+static inline int grid_for(int nitems, int cap) {
+  if (nitems <= 0) return 0;
+  return (cap > 0 && cap < nitems) ? cap : nitems;
+}
+
+template <typename T>
+static Tables<T> tables(const DevPlan& p) {
+  Tables<T> t;
+  t.box = p.box;
+  t.nsub = p.nsub;
+  t.plans = p.plans;
+  t.tw = reinterpret_cast<const cx<T>*>(p.tw);
+  t.idx = p.idx;
+  t.kmod = p.kmod;
+  return t;
+}
+
+template <typename T, int NT, int PB>
+static hipError_t set_upd_attr(int lds) {
+  hipError_t e = hipSuccess;
+  e = hipFuncSetAttribute((const void*)k_z_update<T, NT, PB, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_z_update<T, NT, PB, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_z_update<T, NT, PB, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_z_update<T, NT, PB, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_z_update<T, NT, PB, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_z_update<T, NT, PB, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
+hipError_t prepare_kernels(bool f64, int ldsF, int ldsI, int ldsU, int /*PPT*/) {
+  hipError_t e;
+  if (f64) {
+    if ((e = hipFuncSetAttribute((const void*)k_fwd_xy<double>, hipFuncAttributeMaxDynamicSharedMemorySize, ldsF)) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute((const void*)k_inv_xy<double>, hipFuncAttributeMaxDynamicSharedMemorySize, ldsI)) != hipSuccess) return e;
+    return set_upd_attr<double, kThreadsU64, kPB64>(ldsU);
+  }
+  if ((e = hipFuncSetAttribute((const void*)k_fwd_xy<float>, hipFuncAttributeMaxDynamicSharedMemorySize, ldsF)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_inv_xy<float>, hipFuncAttributeMaxDynamicSharedMemorySize, ldsI)) != hipSuccess) return e;
+  return set_upd_attr<float, kThreadsU32, kPB32>(ldsU);
+}
+
+// ---------------------------------------------------------------- launchers
+template <typename T>
+static hipError_t fill_t(const DevPlan& p, void* const* comps, int ncomp, hipStream_t st) {
+  FillArgs<T> a;
+  a.box = p.box;
+  a.nsub = p.nsub;
+  a.items = p.itemsP;
+  a.own = p.own;
+  a.ncomp = ncomp;
+  for (int c = 0; c < 9; ++c) a.comp[c] = (c < ncomp) ? reinterpret_cast<T*>(comps[c]) : nullptr;
+  const int g = grid_for(p.nP, p.grid_cap[kPhaseExchEB]);
+  if (!g) return hipSuccess;
+  hipLaunchKernelGGL(k_fill<T>, dim3(g), dim3(kThreadsXY), 0, st, a, p.nP);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(const DevPlan& p, void* const* comps, int ncomp, hipStream_t st) {
+  return p.f64 ? fill_t<double>(p, comps, ncomp, st) : fill_t<float>(p, comps, ncomp, st);
+}
+
+template <typename T>
+static hipError_t sum_t(const DevPlan& p, void* const* J, hipStream_t st) {
+  SumArgs<T> a;
+  a.box = p.box;
+  a.nsub = p.nsub;
+  a.items = p.itemsN;
+  a.nbr_off = p.nbr_off;
+  a.nbr = p.nbr;
+  for (int u = 0; u < 3; ++u) a.N[u] = p.N[u];
+  for (int c = 0; c < 3; ++c) a.comp[c] = reinterpret_cast<T*>(J[c]);
+  const int g = grid_for(p.nN, p.grid_cap[kPhaseExchJ]);
+  if (!g) return hipSuccess;
+  hipLaunchKernelGGL(k_sum<T>, dim3(g), dim3(kThreadsXY), 0, st, a, p.nN);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum(const DevPlan& p, void* const* J, hipStream_t st) {
+  return p.f64 ? sum_t<double>(p, J, st) : sum_t<float>(p, J, st);
+}
+
+template <typename T>
+static hipError_t fwd_t(const DevPlan& p, void* const* in9, void* spec, hipStream_t st) {
+  FwdArgs<T> a;
+  a.t = tables<T>(p);
+  a.items = p.itemsF;
+  a.nfield = 9;
+  for (int f = 0; f < 9; ++f) a.in[f] = reinterpret_cast<const T*>(in9[f]);
+  a.spec = reinterpret_cast<cx<T>*>(spec);
+  a.slab = p.slab;
+  const int g = grid_for(p.nF, p.grid_cap[kPhaseFwd]);
+  if (!g) return hipSuccess;
+  hipLaunchKernelGGL(k_fwd_xy<T>, dim3(g), dim3(kThreadsXY), p.ldsF, st, a, p.nF);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd(const DevPlan& p, void* const* in9, void* spec, hipStream_t st) {
+  return p.f64 ? fwd_t<double>(p, in9, spec, st) : fwd_t<float>(p, in9, spec, st);
+}
+
+template <typename T, int NT, int PB>
+static hipError_t upd_t(const DevPlan& p, void* spec, hipStream_t st) {
+  UpdArgs<T> a;
+  a.t = tables<T>(p);
+  a.items = p.itemsU;
+  a.spec = reinterpret_cast<cx<T>*>(spec);
+  a.slab = p.slab;
+  a.k.c = p.c;
+  a.k.dt = p.dt;
+  const int g = grid_for(p.nU, p.grid_cap[kPhaseUpd]);
+  if (!g) return hipSuccess;
+  switch (p.PPT) {
+    case 1: hipLaunchKernelGGL((k_z_update<T, NT, PB, 1>), dim3(g), dim3(NT), p.ldsU, st, a, p.nU); break;
+    case 2: hipLaunchKernelGGL((k_z_update<T, NT, PB, 2>), dim3(g), dim3(NT), p.ldsU, st, a, p.nU); break;
+    case 3: hipLaunchKernelGGL((k_z_update<T, NT, PB, 3>), dim3(g), dim3(NT), p.ldsU, st, a, p.nU); break;
+    case 4: hipLaunchKernelGGL((k_z_update<T, NT, PB, 4>), dim3(g), dim3(NT), p.ldsU, st, a, p.nU); break;
+    case 5: hipLaunchKernelGGL((k_z_update<T, NT, PB, 5>), dim3(g), dim3(NT), p.ldsU, st, a, p.nU); break;
+    case 6: hipLaunchKernelGGL((k_z_update<T, NT, PB, 6>), dim3(g), dim3(NT), p.ldsU, st, a, p.nU); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_upd(const DevPlan& p, void* spec, hipStream_t st) {
+  return p.f64 ? upd_t<double, kThreadsU64, kPB64>(p, spec, st)
+               : upd_t<float, kThreadsU32, kPB32>(p, spec, st);
+}
+
+template <typename T>
+static hipError_t inv_t(const DevPlan& p, const void* spec, void* const* out6, hipStream_t st) {
+  InvArgs<T> a;
+  a.t = tables<T>(p);
+  a.items = p.itemsI;
+  a.spec = reinterpret_cast<const cx<T>*>(spec);
+  a.slab = p.slab;
+  for (int f = 0; f < 6; ++f) a.out[f] = reinterpret_cast<T*>(out6[f]);
+  const int g = grid_for(p.nI, p.grid_cap[kPhaseInv]);
+  if (!g) return hipSuccess;
+  hipLaunchKernelGGL(k_inv_xy<T>, dim3(g), dim3(kThreadsXY), p.ldsI, st, a, p.nI);
+  return hipGetLastError();
+}
+
+hipError_t launch_inv(const DevPlan& p, const void* spec, void* const* out6, hipStream_t st) {
+  return p.f64 ? inv_t<double>(p, spec, out6, st) : inv_t<float>(p, spec, out6, st);
+}
+
+template <typename T>
+static hipError_t scat_t(const DevPlan& p, const void* const* src, void* const* dst, bool scatter,
+                         hipStream_t st) {
+  ScatterArgs<T> a;
+  a.box = p.box;
+  a.nsub = p.nsub;
+  a.items = scatter ? p.itemsP : p.itemsN;
+  for (int u = 0; u < 3; ++u) a.N[u] = p.N[u];
+  for (int c = 0; c < 3; ++c) {
+    a.src[c] = reinterpret_cast<const T*>(src[c]);
+    a.dst[c] = reinterpret_cast<T*>(dst[c]);
+  }
+  const int n = scatter ? p.nP : p.nN;
+  if (!n) return hipSuccess;
+  if (scatter)
+    hipLaunchKernelGGL(k_scatter<T>, dim3(n), dim3(kThreadsXY), 0, st, a, n);
+  else
+    hipLaunchKernelGGL(k_gather<T>, dim3(n), dim3(kThreadsXY), 0, st, a, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const DevPlan& p, const void* const* glob, void* const* pad, hipStream_t st) {
+  return p.f64 ? scat_t<double>(p, glob, pad, true, st) : scat_t<float>(p, glob, pad, true, st);
+}
+
+hipError_t launch_gather(const DevPlan& p, const void* const* pad, void* const* glob, hipStream_t st) {
+  return p.f64 ? scat_t<double>(p, pad, glob, false, st) : scat_t<float>(p, pad, glob, false, st);
+}
+
+hipError_t launch_modk(const KEntry* entries, int nent, int maxN, int order_p, double* kmod,
+                       hipStream_t st) {
+  if (nent <= 0) return hipSuccess;
+  const int bx = (maxN + 255) / 256;
+  hipLaunchKernelGGL(k_modk, dim3(bx, nent), dim3(256), 0, st, entries, nent, maxN, order_p, kmod);
+  return hipGetLastError();
+}
+
+}  // namespace psatd

@@ -1,0 +1,49 @@
+// Device-side view of a plan and the launchers of every phase of the step.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "psatd_device.hpp"
+
+namespace psatd {
+
+enum Phase { kPhaseExchJ = 0, kPhaseFwd = 1, kPhaseUpd = 2, kPhaseInv = 3, kPhaseExchEB = 4, kNumPhases = 5 };
+
+struct DevPlan {
+  bool f64;                 // element type: double (true) or float
+  int32_t nsub;
+  int32_t N[3];
+  const BoxD* box;
+  const FftPlanD* plans;
+  const void* tw;           // cx<double> or cx<float> twiddles
+  const int32_t* idx;
+  const double* kmod;
+  OwnerD own;
+  const int32_t* nbr_off;
+  const int32_t* nbr;
+  const int32_t* itemsF;    // P[2] * 9
+  const int32_t* itemsU;    // ceil(P[1] H / PB)
+  const int32_t* itemsI;    // n[2] * 6
+  const int32_t* itemsP;    // P[2]
+  const int32_t* itemsN;    // n[2]
+  int32_t nF, nU, nI, nP, nN;
+  int32_t ldsF, ldsI, ldsU;  // dynamic LDS bytes per work-group
+  int32_t PB, PPT;           // pencils per z-update work-group, points per thread
+  int64_t slab;              // complex elements of one spectral field slab
+  double c, dt;
+  int32_t grid_cap[kNumPhases];  // 0: one work-group per item; else persistent grid
+};
+
+hipError_t launch_fill(const DevPlan& p, void* const* comps, int ncomp, hipStream_t st);
+hipError_t launch_sum(const DevPlan& p, void* const* J, hipStream_t st);
+hipError_t launch_fwd(const DevPlan& p, void* const* in9, void* spec, hipStream_t st);
+hipError_t launch_upd(const DevPlan& p, void* spec, hipStream_t st);
+hipError_t launch_inv(const DevPlan& p, const void* spec, void* const* out6, hipStream_t st);
+hipError_t launch_scatter(const DevPlan& p, const void* const* glob, void* const* pad, hipStream_t st);
+hipError_t launch_gather(const DevPlan& p, const void* const* pad, void* const* glob, hipStream_t st);
+hipError_t launch_modk(const KEntry* entries, int nent, int maxN, int order_p, double* kmod,
+                       hipStream_t st);
+hipError_t prepare_kernels(bool f64, int ldsF, int ldsI, int ldsU, int PPT);
+
+
+}  // namespace psatd

@@ -1,0 +1,219 @@
+"""Python binding of libpsatd.so (ctypes).
+
+Argument marshalling only: every step of the field push runs in the HIP
+library.  PyTorch supplies device memory (``tensor.data_ptr()``) and the stream
+(``torch.cuda.current_stream().cuda_stream``).  If the library is missing the
+import of this module raises; there is no fallback.
+
+Names follow the C-ABI in include/psatd.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpsatd.so")
+
+F64, F32_VALU, F32_BF16X3, F32_BF16X6 = 0, 1, 2, 3
+J_REPLICATED, J_DEPOSITED = 0, 1
+PRECISIONS = {"f64": F64, "f32": F32_VALU, "f32_valu": F32_VALU,
+              "bf16x3": F32_BF16X3, "bf16x6": F32_BF16X6}
+JMODES = {"replicated": J_REPLICATED, "deposited": J_DEPOSITED}
+PHASES = ("exchange_J", "fft_xy_fwd", "z_update", "fft_xy_inv", "exchange_EB")
+NPHASES = len(PHASES)
+
+STATUS = {0: "PSATD_OK", 1: "PSATD_E_INVALID", 2: "PSATD_E_NOMEM", 3: "PSATD_E_HIP",
+          4: "PSATD_E_UNSUPPORTED", 5: "PSATD_E_STATE"}
+
+SYMBOLS = ("psatd_plan", "psatd_validate", "psatd_field_elems", "psatd_field_layout",
+           "psatd_workspace_bytes", "psatd_set_workspace", "psatd_step", "psatd_run",
+           "psatd_run_profiled", "psatd_scatter", "psatd_gather", "psatd_modified_k",
+           "psatd_set_stream", "psatd_sync", "psatd_destroy", "psatd_status_string",
+           "psatd_last_error", "psatd_version")
+
+
+class PsatdError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1707_08500_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    I64P = ctypes.POINTER(ctypes.c_int64)
+    I32P = ctypes.POINTER(ctypes.c_int32)
+    DP = ctypes.POINTER(ctypes.c_double)
+    VPP = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "psatd_plan": ([ctypes.POINTER(P), I64P, DP, i32, I64P, I64P, I32P, i32, f64, f64, i32, i32, P], i32),
+        "psatd_validate": ([I64P, DP, i32, I64P, I64P, I32P, i32, f64, f64, i32, i32, I64P], i32),
+        "psatd_field_elems": ([P, I64P], i32),
+        "psatd_field_layout": ([P, i32, I64P, I64P], i32),
+        "psatd_workspace_bytes": ([P, I64P], i32),
+        "psatd_set_workspace": ([P, P, i64], i32),
+        "psatd_step": ([P, VPP, VPP, VPP], i32),
+        "psatd_run": ([P, VPP, VPP, VPP, i32], i32),
+        "psatd_run_profiled": ([P, VPP, VPP, VPP, i32, DP], i32),
+        "psatd_scatter": ([P, VPP, VPP], i32),
+        "psatd_gather": ([P, VPP, VPP], i32),
+        "psatd_modified_k": ([P, i32, i32, DP, i64], i32),
+        "psatd_set_stream": ([P, P], i32),
+        "psatd_sync": ([P], i32),
+        "psatd_destroy": ([P], None),
+        "psatd_status_string": ([i32], ctypes.c_char_p),
+        "psatd_last_error": ([P], ctypes.c_char_p),
+        "psatd_version": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+LIB = _load()
+
+
+def _check(st, plan=None):
+    if st != 0:
+        msg = LIB.psatd_last_error(plan).decode()
+        raise PsatdError(st, msg)
+
+
+def _arrays(grid_n, grid_d, lo, n, guard):
+    gn = (ctypes.c_int64 * 3)(*[int(v) for v in grid_n])
+    gd = (ctypes.c_double * 3)(*[float(v) for v in grid_d])
+    lo = np.ascontiguousarray(lo, dtype=np.int64).reshape(-1, 3)
+    n = np.ascontiguousarray(n, dtype=np.int64).reshape(-1, 3)
+    guard = np.ascontiguousarray(guard, dtype=np.int32).reshape(-1, 3)
+    if not (lo.shape == n.shape == guard.shape):
+        raise ValueError("lo, n, guard must all be (nsub, 3)")
+    return gn, gd, lo, n, guard
+
+
+def validate(grid_n, grid_d, lo, n, guard, order_p, dt, c=1.0, precision="f64",
+             jmode="replicated"):
+    """Host-side plan checks (no device).  Returns the field-buffer element count."""
+    gn, gd, lo, n, guard = _arrays(grid_n, grid_d, lo, n, guard)
+    out = ctypes.c_int64(0)
+    st = LIB.psatd_validate(gn, gd, lo.shape[0],
+                            lo.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                            n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                            guard.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                            int(order_p), float(dt), float(c), PRECISIONS[precision],
+                            JMODES[jmode], ctypes.byref(out))
+    _check(st)
+    return out.value
+
+
+def _ptrs(tensors):
+    if len(tensors) != 3:
+        raise ValueError("need 3 component buffers")
+    return (ctypes.c_void_p * 3)(*[t.data_ptr() for t in tensors])
+
+
+class Plan:
+    """psatd_plan(grid, decomposition, guard cells, order p, dt, c) and the calls on it."""
+
+    def __init__(self, grid_n, grid_d, lo, n, guard, order_p, dt, c=1.0, precision="f64",
+                 jmode="replicated", stream=None):
+        import torch
+        gn, gd, lo, n, guard = _arrays(grid_n, grid_d, lo, n, guard)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "f64" else torch.float32
+        self.nsub = lo.shape[0]
+        self.grid_n = tuple(int(v) for v in grid_n)
+        h = ctypes.c_void_p()
+        st = LIB.psatd_plan(ctypes.byref(h), gn, gd, self.nsub,
+                            lo.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                            n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                            guard.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                            int(order_p), float(dt), float(c), PRECISIONS[precision],
+                            JMODES[jmode], ctypes.c_void_p(stream))
+        _check(st)
+        self._h = h
+        e = ctypes.c_int64(0)
+        _check(LIB.psatd_field_elems(self._h, ctypes.byref(e)), self._h)
+        self.field_elems = e.value
+
+    # -- layout
+    def layout(self, s):
+        pn = (ctypes.c_int64 * 3)()
+        off = ctypes.c_int64(0)
+        _check(LIB.psatd_field_layout(self._h, int(s), pn, ctypes.byref(off)), self._h)
+        return tuple(pn), off.value
+
+    def workspace_bytes(self):
+        b = ctypes.c_int64(0)
+        _check(LIB.psatd_workspace_bytes(self._h, ctypes.byref(b)), self._h)
+        return b.value
+
+    def set_workspace(self, tensor):
+        if tensor is None:
+            _check(LIB.psatd_set_workspace(self._h, None, 0), self._h)
+        else:
+            _check(LIB.psatd_set_workspace(self._h, ctypes.c_void_p(tensor.data_ptr()),
+                                           tensor.numel() * tensor.element_size()), self._h)
+
+    def empty_fields(self, device="cuda"):
+        import torch
+        return [torch.zeros(self.field_elems, dtype=self.dtype, device=device) for _ in range(3)]
+
+    # -- the step
+    def step(self, E, B, J):
+        _check(LIB.psatd_step(self._h, _ptrs(E), _ptrs(B), _ptrs(J)), self._h)
+
+    def run(self, E, B, J, nsteps):
+        _check(LIB.psatd_run(self._h, _ptrs(E), _ptrs(B), _ptrs(J), int(nsteps)), self._h)
+
+    def run_profiled(self, E, B, J, nsteps):
+        out = (ctypes.c_double * NPHASES)()
+        _check(LIB.psatd_run_profiled(self._h, _ptrs(E), _ptrs(B), _ptrs(J), int(nsteps), out),
+               self._h)
+        return dict(zip(PHASES, list(out)))
+
+    def scatter(self, glob, padded):
+        _check(LIB.psatd_scatter(self._h, _ptrs(glob), _ptrs(padded)), self._h)
+
+    def gather(self, padded, glob):
+        _check(LIB.psatd_gather(self._h, _ptrs(padded), _ptrs(glob)), self._h)
+
+    def modified_k(self, s, axis):
+        pn, _ = self.layout(s)
+        out = np.zeros(pn[axis], dtype=np.float64)
+        _check(LIB.psatd_modified_k(self._h, int(s), int(axis),
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    int(pn[axis])), self._h)
+        return out
+
+    def set_stream(self, stream):
+        _check(LIB.psatd_set_stream(self._h, ctypes.c_void_p(stream)), self._h)
+
+    def sync(self):
+        _check(LIB.psatd_sync(self._h), self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            LIB.psatd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- host helpers (views of the padded layout, no arithmetic)
+    def box_view(self, buf, s):
+        """View of subdomain s inside a 1-D field buffer as [z][y][x]."""
+        (px, py, pz), off = self.layout(s)
+        return buf[off:off + px * py * pz].view(pz, py, px)

@@ -1,0 +1,271 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle.
+
+Bars: FP64 path <= 1e-12 relative L2 per field component against the
+decomposed oracle (O-local); FP32 path <= 1e-5; copies (scatter, gather,
+exchanges) bit-exact; modified-wavenumber tables <= 1e-14.
+"""
+import numpy as np
+import pytest
+
+from oracle import psatd_oracle as O
+from paper_1707_08500_amd import synth
+
+from psatd_cases import GpuCase, boxes_rel_l2, config2_fields, random_fields, say
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1707_08500_amd import psatd  # noqa: F401  (raises if the library is missing)
+    yield
+
+
+# ----------------------------------------------------------- (a1) tables
+@pytest.mark.parametrize("N,du,p", [(96, 1.0, 32), (176, 0.5, 100), (80, 2.0, 64), (32, 1.0, 0),
+                                    (33, 1.0, 16), (22, 0.7, 2)])
+def test_modified_k_table(N, du, p):
+    from paper_1707_08500_amd import psatd
+    say(f"modified_k N={N} du={du} p={p}")
+    plan = psatd.Plan((N, 8, 8), (du, 1.0, 1.0), [[0, 0, 0]], [[N, 8, 8]], [[0, 0, 0]],
+                      p, 0.5) if N % 2 == 0 else None
+    if plan is None:  # odd x length is not a supported R2C axis: test it on y
+        plan = psatd.Plan((8, N, 8), (1.0, du, 1.0), [[0, 0, 0]], [[8, N, 8]], [[0, 0, 0]], p, 0.5)
+        got = plan.modified_k(0, 1)
+    else:
+        got = plan.modified_k(0, 0)
+    ref = O.modified_k(N, du, p)
+    assert np.abs(got - ref).max() <= 1e-14 * max(1.0, np.abs(ref).max())
+    plan.close()
+
+
+# ------------------------------------------------------- layout / copies
+def uneven_small():
+    N = (10, 5, 6)
+    lo = [[0, 0, 0], [4, 0, 0], [0, 2, 0], [4, 2, 0], [0, 0, 4], [4, 0, 4], [0, 2, 4], [4, 2, 4]]
+    n = [[4, 2, 4], [6, 2, 4], [4, 3, 4], [6, 3, 4], [4, 2, 2], [6, 2, 2], [4, 3, 2], [6, 3, 2]]
+    g = [[1, 1, 1], [2, 3, 1], [4, 1, 2], [0, 2, 3], [3, 3, 3], [1, 0, 5], [2, 2, 2], [5, 4, 1]]
+    return N, np.array(lo), np.array(n), np.array(g)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_scatter_gather_exact(precision):
+    say(f"scatter/gather {precision}")
+    N, lo, n, g = uneven_small()
+    E, B, J = random_fields(N, 1)
+    case = GpuCase(N, lo, n, g, 4, 0.3, 1.0, precision, "replicated", E, B, J)
+    cast = (lambda x: x) if precision == "f64" else (lambda x: x.astype(np.float32).astype(np.float64))
+    ref = O.scatter(cast(E), case.dec)
+    got = case.boxes(case.E)
+    for s in range(case.dec.nsub):
+        assert np.array_equal(got[s], ref[s]), s
+    assert np.array_equal(case.gathered(case.E), cast(E))
+
+
+# ---------------------------------------------------- step vs the oracle
+def run_both(N, lo, n, g, p, dt, c, precision, jmode, fields, steps, d=(1.0, 1.0, 1.0),
+             J_boxes=None):
+    E, B, J = fields
+    case = GpuCase(N, lo, n, g, p, dt, c, precision, jmode, E, B, J, d=d)
+    if J_boxes is not None:  # deposited partial currents per copy
+        import torch
+        for a in range(3):
+            host = np.concatenate([J_boxes[s][a].ravel() for s in range(case.dec.nsub)])
+            case.J[a].copy_(torch.from_numpy(host).to("cuda", case.dtype))
+    for _ in range(steps):
+        case.plan.step(case.E, case.B, case.J)
+    case.plan.sync()
+    dec = case.dec
+    Jb = J_boxes if J_boxes is not None else O.scatter(J, dec)
+    oE, oB, oJ = O.run_local(O.scatter(E, dec), O.scatter(B, dec), Jb, dec, d, p, c, dt, steps,
+                             jmode)
+    gE, gB, gJ = case.boxes(case.E), case.boxes(case.B), case.boxes(case.J)
+    return case, boxes_rel_l2(gE, oE), boxes_rel_l2(gB, oB), (gJ, oJ)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_step_uniform_boxes(precision, tol):
+    """2x2x2 boxes of 24^3 with 8 guards (local 40^3), p = 32, 3 steps."""
+    say(f"uniform 48^3 2x2x2 g=8 p=32 {precision}")
+    N = (48, 48, 48)
+    lo, n, g = synth.uniform_decomposition(N, (2, 2, 2), 8)
+    fields = random_fields(N, 3, p=32)
+    _, eE, eB, _ = run_both(N, lo, n, g, 32, 0.5, 1.0, precision, "replicated", fields, 3)
+    say(f"  rel-L2 E {eE} B {eB}")
+    assert max(eE + eB) <= tol
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_step_uneven_deposited(precision, tol):
+    """Uneven boxes, guards wider than neighbours, padded boxes longer than
+    the grid; deposited currents split randomly among their copies."""
+    say(f"uneven deposited {precision}")
+    N, lo, n, g = uneven_small()
+    dec = O.Decomposition(N, lo, n, g)
+    E, B, J = random_fields(N, 4, p=4)
+    Jrep = O.scatter(J, dec)
+    r = synth.rng(5, synth.STREAM_PART)
+    wts = [r.exponential(size=Jb.shape[1:]) for Jb in Jrep]
+    wsum = np.zeros((N[2], N[1], N[0]))
+    for s in range(dec.nsub):
+        ix, iy, iz = dec.global_index(s)
+        Z, Y, X = np.meshgrid(iz, iy, ix, indexing="ij")
+        np.add.at(wsum, (Z, Y, X), wts[s])
+    Jdep = []
+    for s in range(dec.nsub):
+        ix, iy, iz = dec.global_index(s)
+        Z, Y, X = np.meshgrid(iz, iy, ix, indexing="ij")
+        Jdep.append(J[:, Z, Y, X] * wts[s] / wsum[Z, Y, X])
+    if precision == "f32":
+        Jdep = [j.astype(np.float32).astype(np.float64) for j in Jdep]
+        E, B = (x.astype(np.float32).astype(np.float64) for x in (E, B))
+    _, eE, eB, (gJ, oJ) = run_both(N, lo, n, g, 4, 0.3, 1.3, precision, "deposited", (E, B, J), 2,
+                                   J_boxes=Jdep)
+    say(f"  rel-L2 E {eE} B {eB}")
+    assert max(eE + eB) <= tol
+    jerr = boxes_rel_l2(gJ, oJ)
+    assert max(jerr) <= (1e-14 if precision == "f64" else 1e-6)
+
+
+def test_step_infinite_order_and_odd_lengths():
+    """p = infinity; padded lengths 2*3*5, 7, 11 on uneven axes."""
+    say("p=inf odd radices")
+    N = (30, 14, 22)
+    lo = [[0, 0, 0], [14, 0, 0], [0, 7, 0], [14, 7, 0]]
+    n = [[14, 7, 22], [16, 7, 22], [14, 7, 22], [16, 7, 22]]
+    g = [[8, 0, 0], [7, 0, 0], [8, 0, 0], [7, 0, 0]]
+    fields = random_fields(N, 6, p=0)
+    _, eE, eB, _ = run_both(N, np.array(lo), np.array(n), np.array(g), 0, 0.4, 1.0, "f64",
+                            "replicated", fields, 2)
+    say(f"  rel-L2 E {eE} B {eB}")
+    assert max(eE + eB) <= TOL64
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_step_local_96_cubed(precision, tol):
+    """The configuration-2 local shape (64^3 + 16 guards = 96^3, p = 32) on a
+    128^3 grid of 2x2x2 boxes with the configuration-2 input recipe."""
+    say(f"128^3 2x2x2 g=16 p=32 {precision}")
+    N = (128, 128, 128)
+    d = (1.0, 1.0, 1.0)
+    lo, n, g = synth.uniform_decomposition(N, (2, 2, 2), 16)
+    fields = config2_fields(N, d, 32)
+    _, eE, eB, _ = run_both(N, lo, n, g, 32, 0.5, 1.0, precision, "replicated", fields, 2)
+    say(f"  rel-L2 E {eE} B {eB}")
+    assert max(eE + eB) <= tol
+
+
+# ------------------------------------------- configuration 1: closed form
+def config1_waves(p, N=32, count=8):
+    ms, amps, phases = synth.wave_parameters(case=1, count=count, mmax=15,
+                                             exclude_nyquist_of=(N, N, N))
+    out = []
+    for m, a, ph in zip(ms, amps, phases):
+        kv = np.array([O.modified_k(N, 1.0, p)[m[u] % N] for u in range(3)])
+        a = O.project_transverse(a, kv)
+        out.append((m, a / np.linalg.norm(a), ph, kv))
+    return out
+
+
+def wave_fields(waves, N, c, t):
+    E = np.zeros((3, N, N, N))
+    B = np.zeros((3, N, N, N))
+    for m, a, ph, kv in waves:
+        w = c * np.linalg.norm(kv)
+        E += synth.plane_wave((N, N, N), m, a, ph, t_phase=w * t)
+        B += synth.plane_wave((N, N, N), m, np.cross(kv / np.linalg.norm(kv), a) / c, ph, t_phase=w * t)
+    return E, B
+
+
+@pytest.mark.parametrize("p", [0, 16])
+def test_config1_plane_waves_closed_form(p):
+    """32^3 periodic, no decomposition, 8 plane waves, dt = 0.5, 10 steps:
+    the field after n steps is the analytic plane-wave solution with the
+    order-p dispersion relation."""
+    say(f"config 1 p={p}")
+    N, c, dt = 32, 1.0, 0.5
+    waves = config1_waves(p, N)
+    E, B = wave_fields(waves, N, c, 0.0)
+    case = GpuCase((N, N, N), [[0, 0, 0]], [[N, N, N]], [[0, 0, 0]], p, dt, c, "f64", "replicated",
+                   E, B, np.zeros_like(E))
+    case.plan.run(case.E, case.B, case.J, 10)
+    case.plan.sync()
+    Ew, Bw = wave_fields(waves, N, c, 10 * dt)
+    gE, gB = case.gathered(case.E), case.gathered(case.B)
+    say(f"  max |E - closed form| {np.abs(gE - Ew).max():.3e}")
+    assert np.abs(gE - Ew).max() <= 1e-12 * len(waves)
+    assert np.abs(gB - Bw).max() <= 1e-12 * len(waves)
+    # energy and div B
+    assert abs(O.energy(gE, gB, c) - O.energy(*wave_fields(waves, N, c, 0.0), c)) <= \
+        1e-12 * O.energy(gE, gB, c)
+    assert np.abs(O.div_spectral(gB, (1.0, 1.0, 1.0), p)).max() <= 1e-12 * np.abs(O.fft3(gB)).max()
+
+
+# ---------------------------------------- graph, determinism, consistency
+def test_graph_run_equals_eager_steps_and_is_deterministic():
+    say("graph vs eager")
+    N = (32, 32, 32)
+    lo, n, g = synth.uniform_decomposition(N, (2, 2, 2), 4)
+    E, B, J = random_fields(N, 8, p=8)
+    a = GpuCase(N, lo, n, g, 8, 0.5, 1.0, "f32", "replicated", E, B, J)
+    b = GpuCase(N, lo, n, g, 8, 0.5, 1.0, "f32", "replicated", E, B, J)
+    for _ in range(4):
+        a.plan.step(a.E, a.B, a.J)
+    b.plan.run(b.E, b.B, b.J, 2)
+    b.plan.run(b.E, b.B, b.J, 2)  # replay of the cached graph
+    a.plan.sync()
+    b.plan.sync()
+    for x, y in zip(a.E + a.B, b.E + b.B):
+        assert bool((x == y).all())
+
+
+def test_guards_consistent_after_steps():
+    say("consistency after steps")
+    N, lo, n, g = uneven_small()
+    E, B, J = random_fields(N, 9, p=4)
+    case = GpuCase(N, lo, n, g, 4, 0.3, 1.0, "f64", "replicated", E, B, J)
+    case.plan.run(case.E, case.B, case.J, 3)
+    case.plan.sync()
+    got = case.boxes(case.E)
+    ref = O.exchange_fill([got[s] for s in range(case.dec.nsub)], case.dec)
+    for s in range(case.dec.nsub):
+        assert np.array_equal(got[s], ref[s])
+
+
+# ------------------------------- configuration 2 at full size, sampled
+def test_config2_full_size_one_step_sampled_boxes():
+    """256^3, 4x4x4 boxes of 64^3, 16 guards, p = 32, FP64: one step on the
+    GPU in the benchmarked launch configuration; three boxes recomputed by the
+    oracle one at a time."""
+    say("config 2 full size, sampled boxes")
+    N = (256, 256, 256)
+    d = (1.0, 1.0, 1.0)
+    p, dt, c = 32, 0.5, 1.0
+    lo, n, g = synth.uniform_decomposition(N, (4, 4, 4), 16)
+    E, B, J = config2_fields(N, d, p)
+    case = GpuCase(N, lo, n, g, p, dt, c, "f64", "replicated", E, B, J)
+    case.plan.run(case.E, case.B, case.J, 1)
+    case.plan.sync()
+    dec = case.dec
+    sample = [0, 21, 63]
+    gE = case.boxes(case.E, sample)
+    gB = case.boxes(case.B, sample)
+    def box(F, s):
+        ix, iy, iz = dec.global_index(s)
+        return F[:, iz[:, None, None], iy[None, :, None], ix[None, None, :]]
+    for s in sample:
+        pe, pb, pj = box(E, s), box(B, s), box(J, s)
+        e1, b1 = O.step_global(pe, pb, pj, d, p, c, dt)
+        gx, gy, gz = dec.g[s]
+        nx, ny, nz = dec.n[s]
+        sl = (slice(None), slice(gz, gz + nz), slice(gy, gy + ny), slice(gx, gx + nx))
+        errE = [O.rel_l2(gE[s][sl][a], e1[sl][a]) for a in range(3)]
+        errB = [O.rel_l2(gB[s][sl][a], b1[sl][a]) for a in range(3)] if np.any(b1[sl]) else [0.0]
+        say(f"  box {s}: rel-L2 E {errE} B {errB}")
+        assert max(errE + errB) <= TOL64
