@@ -94,3 +94,14 @@ def boxes_rel_l2(got: dict, ref: list):
         den = sum(float(np.sum(ref[s][a] ** 2)) for s in got)
         out.append(np.sqrt(num / den) if den > 0 else np.sqrt(num))
     return out
+
+
+def energy_rel_l2(gE: dict, gB: dict, oE: list, oB: list, c=1.0):
+    """Relative L2 error in the field-energy norm sqrt(|E|^2 + c^2 |B|^2) over
+    all padded cells of the given boxes (the state-level error of a path whose
+    rounding is relative to the whole state, not to each component)."""
+    num = den = 0.0
+    for s in gE:
+        num += float(np.sum((gE[s] - oE[s]) ** 2) + c * c * np.sum((gB[s] - oB[s]) ** 2))
+        den += float(np.sum(oE[s] ** 2) + c * c * np.sum(oB[s] ** 2))
+    return float(np.sqrt(num / den))
