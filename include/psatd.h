@@ -82,6 +82,19 @@ enum {
   PSATD_NPHASES = 5
 };
 
+/* Launch-shape knobs (psatd_set_tuning).  None changes results beyond rounding order. */
+typedef enum {
+  PSATD_TUNE_Z_PENCILS = 0,  /* (ky,kx) pencils per z-update work-group: 2, 4, 8 or 16 (LDS-limited) */
+  PSATD_TUNE_XCD_REMAP = 1,  /* 1: consecutive work items on the same XCD (shared L2); 0: dispatch order */
+  PSATD_TUNE_GRID_FWD = 2,   /* work-groups of the forward x/y pass: 0 = one per item, else a persistent grid */
+  PSATD_TUNE_GRID_UPD = 3,   /* same for the z-update pass */
+  PSATD_TUNE_GRID_INV = 4,   /* same for the inverse y/x pass */
+  PSATD_TUNE_GRID_EXCH = 5,  /* same for the guard exchanges */
+  PSATD_TUNE_BATCH_BOXES = 6, /* subdomains pushed through the FFT/update passes together (0 = all);
+                                 the workspace then holds one batch's half spectra */
+  PSATD_NTUNE = 7
+} psatd_tune_key;
+
 /*
  * psatd_plan -- build a plan (Sec. 3.2 decomposition, Sec. 3.1 operator).
  *   grid_n[3]   global periodic interior cells (Nx, Ny, Nz), each >= 1
@@ -140,13 +153,16 @@ psatd_status psatd_set_workspace(psatd_plan_t plan, void* dev, int64_t bytes);
  * psatd_step -- one step (exchange_J, local push of every padded box, exchange_EB),
  * enqueued on the plan's stream.  E, B, J: arrays of 3 device field buffers.  The
  * state must be consistent on entry (every guard copy equal to its owner, as
- * psatd_scatter leaves it); it is consistent again on exit.
+ * psatd_scatter leaves it); it is consistent again on exit.  In PSATD_J_DEPOSITED mode
+ * every call takes J as freshly deposited partial currents and sums them (after the
+ * call J holds the summed, consistent currents).
  */
 psatd_status psatd_step(psatd_plan_t plan, void* const E[3], void* const B[3], void* const J[3]);
 
 /*
  * psatd_run -- nsteps >= 0 steps with J unchanged, replayed from a captured HIP graph
- * (captured once per (buffers, nsteps) and cached in the plan).
+ * (captured once per (buffers, nsteps) and cached in the plan).  In PSATD_J_DEPOSITED
+ * mode the partial currents are summed once, at the first step, and then held.
  */
 psatd_status psatd_run(psatd_plan_t plan, void* const E[3], void* const B[3], void* const J[3],
                        int32_t nsteps);
@@ -173,6 +189,14 @@ psatd_status psatd_gather(psatd_plan_t plan, const void* const padded[3], void* 
  */
 psatd_status psatd_modified_k(psatd_plan_t plan, int32_t s, int32_t axis, double* out,
                               int64_t len);
+
+/*
+ * psatd_set_tuning / psatd_get_tuning -- launch-shape knobs (psatd_tune_key).  Setting a
+ * value the plan cannot use (e.g. a z tile that does not fit the LDS) returns
+ * PSATD_E_INVALID and leaves the plan unchanged.  Cached graphs are dropped.
+ */
+psatd_status psatd_set_tuning(psatd_plan_t plan, int32_t key, int32_t value);
+psatd_status psatd_get_tuning(psatd_plan_t plan, int32_t key, int32_t* value);
 
 psatd_status psatd_set_stream(psatd_plan_t plan, void* stream);
 psatd_status psatd_sync(psatd_plan_t plan); /* waits for the plan's stream */

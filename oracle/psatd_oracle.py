@@ -334,8 +334,11 @@ def step_local(Eb, Bb, Jb, dec, d, p, c, dt, jmode="replicated"):
 
 
 def run_local(Eb, Bb, Jb, dec, d, p, c, dt, nsteps, jmode="replicated"):
-    for _ in range(nsteps):
-        Eb, Bb, Jb = step_local(Eb, Bb, Jb, dec, d, p, c, dt, jmode)
+    """nsteps steps with J held fixed.  Deposited partial currents are summed
+    once, at the first step; the summed (consistent) J is then held, i.e. the
+    later steps use the replicated mode, which leaves a consistent J as is."""
+    for i in range(nsteps):
+        Eb, Bb, Jb = step_local(Eb, Bb, Jb, dec, d, p, c, dt, jmode if i == 0 else "replicated")
     return Eb, Bb, Jb
 
 

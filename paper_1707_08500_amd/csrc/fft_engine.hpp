@@ -142,15 +142,61 @@ template <int DIR, typename T> struct Dft<16, DIR, T> : DftSplit<4, 4, DIR, T> {
 // ------------------------------------------------------------------ plans
 constexpr int kMaxStages = 4;
 
-// One FFT length's schedule; tables live in the plan's device buffers.
+// n / d by a multiply-high: m = ceil(2^32 / d) makes floor(n m / 2^32) equal
+// to n/d or n/d + 1 for every 32-bit n, so one correction gives the exact
+// quotient (valid while n + d < 2^32).  d == 1 is the identity.
+struct FastDiv {
+  uint32_t d, m;
+};
+PSATD_HD FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  f.m = d > 1 ? 0xFFFFFFFFu / d + 1u : 0u;
+  return f;
+}
+PSATD_HD uint32_t fdiv(uint32_t n, FastDiv f) {
+  if (f.d == 1u) return n;
+  const uint32_t q = (uint32_t)(((uint64_t)n * f.m) >> 32);
+  return (q * f.d > n) ? q - 1u : q;
+}
+
+// One FFT length's schedule.  Stage s has radix r_s and stride
+// ms_s = N / (r_0 ... r_s); twiddles live in the plan's table at offset tw.
 struct FftPlanD {
   int32_t N;
   int32_t nstages;
   int32_t radix[kMaxStages];
+  int32_t stride[kMaxStages];   // ms_s
+  int32_t prod[kMaxStages];     // r_0 ... r_{s-1}
+  FastDiv rdiv[kMaxStages];     // division by r_s
+  FastDiv sdiv[kMaxStages];     // division by ms_s
   int32_t tw;    // offset of W_N^e = exp(-2 pi i e / N), e = 0..N-1, in the twiddle table
-  int32_t pos;   // offset of pos(k), k = 0..N-1, in the index table
-  int32_t ipos;  // offset of the inverse map (position -> index)
+  int32_t pad_;
 };
+
+// Position of index k in stage-digit order: k = t_0 + r_0 t_1 + ..., pos = sum t_s ms_s.
+PSATD_HD int plan_pos(const FftPlanD* pl, int k) {
+  int pos = 0;
+  uint32_t rem = (uint32_t)k;
+  for (int s = 0; s < pl->nstages; ++s) {
+    const uint32_t q = fdiv(rem, pl->rdiv[s]);
+    pos += (int)(rem - q * (uint32_t)pl->radix[s]) * pl->stride[s];
+    rem = q;
+  }
+  return pos;
+}
+
+// Inverse of plan_pos: the index held at position p.
+PSATD_HD int plan_index(const FftPlanD* pl, int p) {
+  int k = 0;
+  uint32_t rem = (uint32_t)p;
+  for (int s = 0; s < pl->nstages; ++s) {
+    const uint32_t t = fdiv(rem, pl->sdiv[s]);
+    rem -= t * (uint32_t)pl->stride[s];
+    k += (int)t * pl->prod[s];
+  }
+  return k;
+}
 
 // twiddle W_N^e for direction DIR from the forward table
 template <int DIR, typename T>
@@ -164,16 +210,16 @@ PSATD_HD cx<T> twid(const cx<T>* tw, int e) {
 // Sub-transform length L, stride L/R.  Butterflies are distributed with the
 // transform index fastest across threads.
 template <int R, int DIR, bool DIF, typename T>
-PSATD_HD void fft_stage(cx<T>* buf, int M, int ms, int es, int N, int L, const cx<T>* tw, int tid,
-                        int nt) {
+PSATD_HD void fft_stage(cx<T>* buf, int M, FastDiv dM, int ms, int es, int N, int L, FastDiv dS,
+                        const cx<T>* tw, int tid, int nt) {
   const int mstride = L / R;
   const int nb = N / R;
   const int twstep = N / L;
   const int total = M * nb;
   for (int b = tid; b < total; b += nt) {
-    const int w = b / M;
+    const int w = (int)fdiv((uint32_t)b, dM);
     const int m = b - w * M;
-    const int blk = w / mstride;
+    const int blk = (int)fdiv((uint32_t)w, dS);
     const int j = w - blk * mstride;
     cx<T>* p = buf + m * ms + (blk * L + j) * es;
     const int step = mstride * es;
@@ -199,36 +245,36 @@ PSATD_HD void fft_stage(cx<T>* buf, int M, int ms, int es, int N, int L, const c
 }
 
 template <int DIR, bool DIF, typename T>
-PSATD_HD void fft_stage_dispatch(int R, cx<T>* buf, int M, int ms, int es, int N, int L,
-                                 const cx<T>* tw, int tid, int nt) {
+PSATD_HD void fft_stage_dispatch(int R, cx<T>* buf, int M, FastDiv dM, int ms, int es, int N, int L,
+                                 FastDiv dS, const cx<T>* tw, int tid, int nt) {
   switch (R) {
-    case 2: fft_stage<2, DIR, DIF>(buf, M, ms, es, N, L, tw, tid, nt); break;
-    case 3: fft_stage<3, DIR, DIF>(buf, M, ms, es, N, L, tw, tid, nt); break;
-    case 4: fft_stage<4, DIR, DIF>(buf, M, ms, es, N, L, tw, tid, nt); break;
-    case 5: fft_stage<5, DIR, DIF>(buf, M, ms, es, N, L, tw, tid, nt); break;
-    case 6: fft_stage<6, DIR, DIF>(buf, M, ms, es, N, L, tw, tid, nt); break;
-    case 7: fft_stage<7, DIR, DIF>(buf, M, ms, es, N, L, tw, tid, nt); break;
-    case 8: fft_stage<8, DIR, DIF>(buf, M, ms, es, N, L, tw, tid, nt); break;
-    case 10: fft_stage<10, DIR, DIF>(buf, M, ms, es, N, L, tw, tid, nt); break;
-    case 11: fft_stage<11, DIR, DIF>(buf, M, ms, es, N, L, tw, tid, nt); break;
-    case 12: fft_stage<12, DIR, DIF>(buf, M, ms, es, N, L, tw, tid, nt); break;
-    case 16: fft_stage<16, DIR, DIF>(buf, M, ms, es, N, L, tw, tid, nt); break;
+    case 2: fft_stage<2, DIR, DIF>(buf, M, dM, ms, es, N, L, dS, tw, tid, nt); break;
+    case 3: fft_stage<3, DIR, DIF>(buf, M, dM, ms, es, N, L, dS, tw, tid, nt); break;
+    case 4: fft_stage<4, DIR, DIF>(buf, M, dM, ms, es, N, L, dS, tw, tid, nt); break;
+    case 5: fft_stage<5, DIR, DIF>(buf, M, dM, ms, es, N, L, dS, tw, tid, nt); break;
+    case 6: fft_stage<6, DIR, DIF>(buf, M, dM, ms, es, N, L, dS, tw, tid, nt); break;
+    case 7: fft_stage<7, DIR, DIF>(buf, M, dM, ms, es, N, L, dS, tw, tid, nt); break;
+    case 8: fft_stage<8, DIR, DIF>(buf, M, dM, ms, es, N, L, dS, tw, tid, nt); break;
+    case 10: fft_stage<10, DIR, DIF>(buf, M, dM, ms, es, N, L, dS, tw, tid, nt); break;
+    case 11: fft_stage<11, DIR, DIF>(buf, M, dM, ms, es, N, L, dS, tw, tid, nt); break;
+    case 12: fft_stage<12, DIR, DIF>(buf, M, dM, ms, es, N, L, dS, tw, tid, nt); break;
+    case 16: fft_stage<16, DIR, DIF>(buf, M, dM, ms, es, N, L, dS, tw, tid, nt); break;
     default: break;  // plans only hold the radices above (checked at plan time)
   }
 }
 
-// natural -> stage-digit order; ends with a barrier.  The plan is read from
-// (uniform) global memory so that no per-thread copy of it is indexed.
+// natural -> stage-digit order; ends with a barrier.  tw: this plan's W_N^e
+// table (global or LDS).  The plan is read from uniform memory.
 template <int DIR, typename T, class Bar>
-PSATD_HD void fft_dif(cx<T>* buf, int M, int ms, int es, const FftPlanD* pl, const cx<T>* twtab,
+PSATD_HD void fft_dif(cx<T>* buf, int M, int ms, int es, const FftPlanD* pl, const cx<T>* tw,
                       int tid, int nt, Bar bar) {
   const int N = pl->N;
   const int ns = pl->nstages;
-  const cx<T>* tw = twtab + pl->tw;
+  const FastDiv dM = make_fastdiv((uint32_t)M);
   int L = N;
   for (int s = 0; s < ns; ++s) {
     const int R = pl->radix[s];
-    fft_stage_dispatch<DIR, true, T>(R, buf, M, ms, es, N, L, tw, tid, nt);
+    fft_stage_dispatch<DIR, true, T>(R, buf, M, dM, ms, es, N, L, pl->sdiv[s], tw, tid, nt);
     bar();
     L /= R;
   }
@@ -236,15 +282,15 @@ PSATD_HD void fft_dif(cx<T>* buf, int M, int ms, int es, const FftPlanD* pl, con
 
 // stage-digit -> natural order; ends with a barrier
 template <int DIR, typename T, class Bar>
-PSATD_HD void fft_dit(cx<T>* buf, int M, int ms, int es, const FftPlanD* pl, const cx<T>* twtab,
+PSATD_HD void fft_dit(cx<T>* buf, int M, int ms, int es, const FftPlanD* pl, const cx<T>* tw,
                       int tid, int nt, Bar bar) {
   const int N = pl->N;
   const int ns = pl->nstages;
-  const cx<T>* tw = twtab + pl->tw;
+  const FastDiv dM = make_fastdiv((uint32_t)M);
   for (int s = ns - 1; s >= 0; --s) {
-    int L = N;
-    for (int i = 0; i < s; ++i) L /= pl->radix[i];
-    fft_stage_dispatch<DIR, false, T>(pl->radix[s], buf, M, ms, es, N, L, tw, tid, nt);
+    const int L = pl->stride[s] * pl->radix[s];
+    fft_stage_dispatch<DIR, false, T>(pl->radix[s], buf, M, dM, ms, es, N, L, pl->sdiv[s], tw, tid,
+                                      nt);
     bar();
   }
 }

@@ -26,7 +26,6 @@ struct HostTables {
   std::vector<BoxD> box;
   std::vector<FftPlanD> plans;
   std::vector<long double> twr, twi;  // all twiddle tables, forward sign
-  std::vector<int32_t> idx;
   std::vector<KEntry> kent;
   int32_t kmod_len = 0;
   int32_t kmax_len = 0;
@@ -35,9 +34,12 @@ struct HostTables {
   std::vector<int32_t> owner;
   std::vector<int32_t> nbr_off, nbr;
   std::vector<int32_t> itemsF, itemsU, itemsI, itemsP, itemsN;
+  std::vector<Batch> batches;
+  int64_t batch_slab = 0;     // complex elements of one spectral field slab of the largest batch
+  int32_t batch_boxes = 0;
   int64_t field_elems = 0;
   int64_t slab = 0;
-  int ldsF = 0, ldsI = 0, ldsU = 0, PB = 0, PPT = 0;
+  int ldsF = 0, ldsI = 0, ldsU = 0, PB = 0, NTU = 0;
 };
 
 inline bool is_f64(int prec) { return prec == PSATD_F64; }
@@ -82,30 +84,27 @@ inline int add_plan(HostTables& h, int N) {
   FftPlanD pl{};
   pl.N = N;
   pl.nstages = (int)rad.size();
-  for (int s = 0; s < kMaxStages; ++s) pl.radix[s] = s < pl.nstages ? rad[s] : 1;
+  int prod = 1;
+  for (int st = 0; st < kMaxStages; ++st) {
+    if (st < pl.nstages) {
+      pl.radix[st] = rad[st];
+      pl.prod[st] = prod;
+      prod *= rad[st];
+      pl.stride[st] = N / prod;
+    } else {
+      pl.radix[st] = 1;
+      pl.prod[st] = prod;
+      pl.stride[st] = 1;
+    }
+    pl.rdiv[st] = make_fastdiv((uint32_t)pl.radix[st]);
+    pl.sdiv[st] = make_fastdiv((uint32_t)pl.stride[st]);
+  }
   pl.tw = (int32_t)h.twr.size();
   const long double PI = 3.141592653589793238462643383279502884L;
   for (int e = 0; e < N; ++e) {
     h.twr.push_back(cosl(2.0L * PI * e / N));
     h.twi.push_back(-sinl(2.0L * PI * e / N));
   }
-  pl.pos = (int32_t)h.idx.size();
-  std::vector<int32_t> pos(N), ipos(N);
-  for (int k = 0; k < N; ++k) {
-    int64_t prod = 1, rem = k, p = 0, Nrem = N;
-    for (int s = 0; s < pl.nstages; ++s) {
-      const int t = (int)(rem % rad[s]);
-      rem /= rad[s];
-      Nrem /= rad[s];
-      p += (int64_t)t * Nrem;
-      prod *= rad[s];
-    }
-    pos[k] = (int32_t)p;
-  }
-  for (int k = 0; k < N; ++k) ipos[pos[k]] = k;
-  h.idx.insert(h.idx.end(), pos.begin(), pos.end());
-  pl.ipos = (int32_t)h.idx.size();
-  h.idx.insert(h.idx.end(), ipos.begin(), ipos.end());
   h.plans.push_back(pl);
   return (int)h.plans.size() - 1;
 }
@@ -135,6 +134,51 @@ inline int add_kentry(HostTables& h, int N, double du) {
   h.kmax_len = std::max(h.kmax_len, N);
   h.kent.push_back(k);
   return k.off;
+}
+
+// Groups of consecutive boxes pushed through the FFT/update passes together.
+inline void set_batches(HostTables& h, int per) {
+  h.batch_boxes = per;
+  if (per <= 0 || per > h.nsub) per = h.nsub;
+  h.batches.clear();
+  h.batch_slab = 0;
+  for (int b0 = 0; b0 < h.nsub; b0 += per) {
+    const int b1 = std::min(h.nsub, b0 + per);
+    Batch b;
+    b.b0 = b0;
+    b.b1 = b1;
+    b.F0 = h.itemsF[b0];
+    b.nF = h.itemsF[b1] - h.itemsF[b0];
+    b.U0 = h.itemsU[b0];
+    b.nU = h.itemsU[b1] - h.itemsU[b0];
+    b.I0 = h.itemsI[b0];
+    b.nI = h.itemsI[b1] - h.itemsI[b0];
+    b.sbias = h.box[b0].soff;
+    const int64_t end = (b1 < h.nsub) ? h.box[b1].soff : h.slab;
+    h.batch_slab = std::max(h.batch_slab, end - b.sbias);
+    h.batches.push_back(b);
+  }
+}
+
+// Work list of the z-update for a tile of PB pencils.
+inline void set_z_tile(HostTables& h, int PB) {
+  const int csz = (int)(2 * real_size(h.prec));
+  int maxPz = 0;
+  h.itemsU.assign(h.nsub + 1, 0);
+  for (int s = 0; s < h.nsub; ++s) {
+    const BoxD& b = h.box[s];
+    h.itemsU[s + 1] = h.itemsU[s] + (int32_t)(((int64_t)b.P[1] * b.H + PB - 1) / PB);
+    maxPz = std::max(maxPz, b.P[2]);
+  }
+  h.PB = PB;
+  h.ldsU = maxPz * (9 * PB + 1) * csz;  // staged fields + the z twiddles
+  if (!h.batches.empty()) set_batches(h, h.batch_boxes);
+}
+
+inline int max_padded_z(const HostTables& h) {
+  int m = 0;
+  for (const BoxD& b : h.box) m = std::max(m, b.P[2]);
+  return m;
 }
 
 // Does the circular interval [a, a+len) (len < N) meet [lo, lo+n) on Z_N?
@@ -257,21 +301,27 @@ inline psatd_status build_host(HostTables& h, std::string& err, const int64_t gr
     b.soff = soff;
     foff += (int64_t)b.P[0] * b.P[1] * b.P[2];
     soff += (int64_t)b.H * b.P[1] * b.P[2];
-    h.ldsF = std::max<int>(h.ldsF, b.P[1] * b.ld * csz);
+    // plane + twiddles of the x plan, the y plan and W_Px
+    h.ldsF = std::max<int>(h.ldsF, (b.P[1] * b.ld + b.P[0] / 2 + b.P[1] + b.P[0]) * csz);
     h.ldsI = h.ldsF;
     maxPz = std::max(maxPz, b.P[2]);
   }
-  if (h.twr.size() > (size_t)INT32_MAX / 2 || h.idx.size() > (size_t)INT32_MAX / 2)
+  if (h.twr.size() > (size_t)INT32_MAX / 2)
     return bad(PSATD_E_UNSUPPORTED, "tables too large");
   h.field_elems = foff;
   h.slab = soff;
   if (h.ldsF > kMaxDynLds)
     return bad(PSATD_E_UNSUPPORTED, "a padded (y, x/2+1) plane exceeds the 160 KiB LDS at this precision");
-  h.PB = f64 ? kPB64 : kPB32;
-  const int NT = f64 ? kThreadsU64 : kThreadsU32;
-  h.PPT = (maxPz * h.PB + NT - 1) / NT;
-  if (h.PPT > kMaxPPT) return bad(PSATD_E_UNSUPPORTED, "padded z length too large for the z-update kernel");
-  h.ldsU = maxPz * h.PB * csz;
+  // z-update tile: PB consecutive (ky, kx) pencils, all 9 fields staged in LDS
+  {
+    int PB = 16;
+    while (PB > 2 && (int64_t)maxPz * (9 * PB + 1) * csz > kMaxDynLds) PB /= 2;
+    if ((int64_t)maxPz * (9 * PB + 1) * csz > kMaxDynLds)
+      return bad(PSATD_E_UNSUPPORTED, "padded z length too large for the z-update kernel");
+    h.PB = PB;
+    h.ldsU = maxPz * (9 * PB + 1) * csz;
+    h.NTU = 512;
+  }
 
   // neighbours: boxes whose padded region meets the interior of s (for the
   // deposited-current sum), ascending
@@ -296,10 +346,11 @@ inline psatd_status build_host(HostTables& h, std::string& err, const int64_t gr
   };
   const int PB = h.PB;
   prefix(h.itemsF, [](const BoxD& b) { return (int64_t)b.P[2] * 9; });
-  prefix(h.itemsU, [PB](const BoxD& b) { return ((int64_t)b.P[1] * b.H + PB - 1) / PB; });
+  set_z_tile(h, PB);
   prefix(h.itemsI, [](const BoxD& b) { return (int64_t)b.n[2] * 6; });
   prefix(h.itemsP, [](const BoxD& b) { return (int64_t)b.P[2]; });
   prefix(h.itemsN, [](const BoxD& b) { return (int64_t)b.n[2]; });
+  set_batches(h, 0);
   return PSATD_OK;
 }
 

@@ -38,6 +38,8 @@ struct psatd_plan_s {
   hipStream_t cap_stream = nullptr;
   int device = 0;
   void* blob = nullptr;  // device tables
+  int32_t* d_itemsU = nullptr;  // z-update work list (depends on the z tile)
+  int32_t tune[PSATD_NTUNE] = {0, 1, 0, 0, 0, 0, 0};
   void* ws = nullptr;
   int64_t ws_bytes = 0;
   bool ws_owned = false;
@@ -61,7 +63,7 @@ psatd_status fail(psatd_plan_t p, psatd_status st, const std::string& m) {
   } while (0)
 
 int64_t workspace_need(const psatd_plan_s* p) {
-  return 9 * p->h.slab * (int64_t)(2 * real_size(p->h.prec));
+  return 9 * p->h.batch_slab * (int64_t)(2 * real_size(p->h.prec));
 }
 
 void drop_graphs(psatd_plan_t p) {
@@ -73,7 +75,14 @@ void drop_graphs(psatd_plan_t p) {
 }
 
 psatd_status ensure_workspace(psatd_plan_t p) {
-  if (p->ws) return PSATD_OK;
+  if (p->ws && p->ws_bytes >= workspace_need(p)) return PSATD_OK;
+  if (p->ws && !p->ws_owned)
+    return fail(p, PSATD_E_INVALID, "caller workspace smaller than psatd_workspace_bytes");
+  if (p->ws) {
+    HIPCHK(p, hipStreamSynchronize(p->stream));
+    HIPCHK(p, hipFree(p->ws));
+    p->ws = nullptr;
+  }
   const int64_t need = workspace_need(p);
   HIPCHK(p, hipMalloc(&p->ws, (size_t)std::max<int64_t>(need, 256)));
   p->ws_bytes = need;
@@ -92,39 +101,49 @@ psatd_status check_fields(psatd_plan_t p, void* const* v, int count, const char*
   return PSATD_OK;
 }
 
-psatd_status enqueue_phase(psatd_plan_t p, int ph, void* const E[3], void* const B[3], void* const J[3],
-                           hipStream_t st) {
+// One step: exchange_J, every batch through F -> U -> I, exchange_EB.  If prof
+// is given, an event pair brackets every launch, tagged with its phase.
+psatd_status enqueue_step(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3],
+                          hipStream_t st, bool deposit,
+                          std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>* prof = nullptr) {
   const DevPlan& d = p->dp;
   void* eb[6] = {E[0], E[1], E[2], B[0], B[1], B[2]};
-  switch (ph) {
-    case kPhaseExchJ:
-      if (p->h.jmode == PSATD_J_DEPOSITED) HIPCHK(p, launch_sum(d, J, st));
-      HIPCHK(p, launch_fill(d, J, 3, st));
-      break;
-    case kPhaseFwd: {
-      void* in9[9] = {E[0], E[1], E[2], B[0], B[1], B[2], J[0], J[1], J[2]};
-      HIPCHK(p, launch_fwd(d, in9, p->ws, st));
-      break;
+  void* in9[9] = {E[0], E[1], E[2], B[0], B[1], B[2], J[0], J[1], J[2]};
+  size_t ip = 0;
+  auto mark = [&](int phase, bool start) -> psatd_status {
+    if (!prof) return PSATD_OK;
+    if (start) {
+      if (ip >= prof->size()) return fail(p, PSATD_E_STATE, "profiling event pool exhausted");
+      (*prof)[ip].first = phase;
+      HIPCHK(p, hipEventRecord((*prof)[ip].second.first, st));
+    } else {
+      HIPCHK(p, hipEventRecord((*prof)[ip].second.second, st));
+      ++ip;
     }
-    case kPhaseUpd:
-      HIPCHK(p, launch_upd(d, p->ws, st));
-      break;
-    case kPhaseInv:
-      HIPCHK(p, launch_inv(d, p->ws, eb, st));
-      break;
-    case kPhaseExchEB:
-      HIPCHK(p, launch_fill(d, eb, 6, st));
-      break;
+    return PSATD_OK;
+  };
+  psatd_status r;
+#define PSATD_MARK(ph, s0) \
+  if ((r = mark(ph, s0)) != PSATD_OK) return r
+  PSATD_MARK(kPhaseExchJ, true);
+  if (deposit) HIPCHK(p, launch_sum(d, J, st));
+  HIPCHK(p, launch_fill(d, J, 3, st));
+  PSATD_MARK(kPhaseExchJ, false);
+  for (const Batch& b : p->h.batches) {
+    PSATD_MARK(kPhaseFwd, true);
+    HIPCHK(p, launch_fwd(d, b, in9, p->ws, st));
+    PSATD_MARK(kPhaseFwd, false);
+    PSATD_MARK(kPhaseUpd, true);
+    HIPCHK(p, launch_upd(d, b, p->ws, st));
+    PSATD_MARK(kPhaseUpd, false);
+    PSATD_MARK(kPhaseInv, true);
+    HIPCHK(p, launch_inv(d, b, p->ws, eb, st));
+    PSATD_MARK(kPhaseInv, false);
   }
-  return PSATD_OK;
-}
-
-psatd_status enqueue_step(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3],
-                          hipStream_t st) {
-  for (int ph = 0; ph < kNumPhases; ++ph) {
-    psatd_status r = enqueue_phase(p, ph, E, B, J, st);
-    if (r != PSATD_OK) return r;
-  }
+  PSATD_MARK(kPhaseExchEB, true);
+  HIPCHK(p, launch_fill(d, eb, 6, st));
+  PSATD_MARK(kPhaseExchEB, false);
+#undef PSATD_MARK
   return PSATD_OK;
 }
 
@@ -209,7 +228,6 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   const size_t o_box = reserve(h.box.size() * sizeof(BoxD));
   const size_t o_plan = reserve(h.plans.size() * sizeof(FftPlanD));
   const size_t o_tw = reserve(h.twr.size() * cs);
-  const size_t o_idx = reserve(h.idx.size() * 4);
   const size_t o_kmod = reserve((size_t)h.kmod_len * 8);
   const size_t o_kent = reserve(h.kent.size() * sizeof(KEntry));
   size_t o_cut[3];
@@ -218,7 +236,6 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   const size_t o_nbo = reserve(h.nbr_off.size() * 4);
   const size_t o_nbr = reserve(std::max<size_t>(h.nbr.size(), 1) * 4);
   const size_t o_iF = reserve(h.itemsF.size() * 4);
-  const size_t o_iU = reserve(h.itemsU.size() * 4);
   const size_t o_iI = reserve(h.itemsI.size() * 4);
   const size_t o_iP = reserve(h.itemsP.size() * 4);
   const size_t o_iN = reserve(h.itemsN.size() * 4);
@@ -237,27 +254,29 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
     for (size_t i = 0; i < t.size(); ++i) t[i] = {(float)h.twr[i], (float)h.twi[i]};
     put(o_tw, t.data(), t.size() * sizeof(cx<float>));
   }
-  put(o_idx, h.idx.data(), h.idx.size() * 4);
   put(o_kent, h.kent.data(), h.kent.size() * sizeof(KEntry));
   for (int u = 0; u < 3; ++u) put(o_cut[u], h.cut[u].data(), h.cut[u].size() * 4);
   put(o_own, h.owner.data(), h.owner.size() * 4);
   put(o_nbo, h.nbr_off.data(), h.nbr_off.size() * 4);
   put(o_nbr, h.nbr.data(), h.nbr.size() * 4);
   put(o_iF, h.itemsF.data(), h.itemsF.size() * 4);
-  put(o_iU, h.itemsU.data(), h.itemsU.size() * 4);
   put(o_iI, h.itemsI.data(), h.itemsI.size() * 4);
   put(o_iP, h.itemsP.data(), h.itemsP.size() * 4);
   put(o_iN, h.itemsN.data(), h.itemsN.size() * 4);
   if ((e = hipMalloc(&p->blob, total)) != hipSuccess) return hipfail(e, "hipMalloc(tables)");
   if ((e = hipMemcpy(p->blob, hb.data(), total, hipMemcpyHostToDevice)) != hipSuccess)
     return hipfail(e, "hipMemcpy(tables)");
+  if ((e = hipMalloc(&p->d_itemsU, h.itemsU.size() * 4)) != hipSuccess) return hipfail(e, "hipMalloc(work list)");
+  if ((e = hipMemcpy(p->d_itemsU, h.itemsU.data(), h.itemsU.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+    return hipfail(e, "hipMemcpy(work list)");
+  p->tune[PSATD_TUNE_Z_PENCILS] = h.PB;
   unsigned char* B = reinterpret_cast<unsigned char*>(p->blob);
   // (a1) modified wavenumbers, FP64, on the device
   if ((e = launch_modk(reinterpret_cast<const KEntry*>(B + o_kent), (int)h.kent.size(), h.kmax_len, h.p,
                        reinterpret_cast<double*>(B + o_kmod), p->cap_stream)) != hipSuccess)
     return hipfail(e, "modified-wavenumber kernel");
   if ((e = hipStreamSynchronize(p->cap_stream)) != hipSuccess) return hipfail(e, "modified-wavenumber kernel");
-  if ((e = prepare_kernels(f64, h.ldsF, h.ldsI, h.ldsU, h.PPT)) != hipSuccess)
+  if ((e = prepare_kernels(f64, h.ldsF, h.ldsI, h.ldsU)) != hipSuccess)
     return hipfail(e, "hipFuncSetAttribute");
 
   DevPlan& d = p->dp;
@@ -268,7 +287,6 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   d.box = reinterpret_cast<const BoxD*>(B + o_box);
   d.plans = reinterpret_cast<const FftPlanD*>(B + o_plan);
   d.tw = B + o_tw;
-  d.idx = reinterpret_cast<const int32_t*>(B + o_idx);
   d.kmod = reinterpret_cast<const double*>(B + o_kmod);
   for (int u = 0; u < 3; ++u) {
     d.own.cut[u] = reinterpret_cast<const int32_t*>(B + o_cut[u]);
@@ -279,7 +297,7 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   d.nbr_off = reinterpret_cast<const int32_t*>(B + o_nbo);
   d.nbr = reinterpret_cast<const int32_t*>(B + o_nbr);
   d.itemsF = reinterpret_cast<const int32_t*>(B + o_iF);
-  d.itemsU = reinterpret_cast<const int32_t*>(B + o_iU);
+  d.itemsU = p->d_itemsU;
   d.itemsI = reinterpret_cast<const int32_t*>(B + o_iI);
   d.itemsP = reinterpret_cast<const int32_t*>(B + o_iP);
   d.itemsN = reinterpret_cast<const int32_t*>(B + o_iN);
@@ -292,8 +310,9 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   d.ldsI = h.ldsI;
   d.ldsU = h.ldsU;
   d.PB = h.PB;
-  d.PPT = h.PPT;
-  d.slab = h.slab;
+  d.NTU = h.NTU;
+  d.xcd = 1;
+  d.slab = h.batch_slab;
   d.c = h.c;
   d.dt = h.dt;
   *out = p;
@@ -305,6 +324,7 @@ void psatd_destroy(psatd_plan_t p) {
   drop_graphs(p);
   if (p->ws_owned && p->ws) (void)hipFree(p->ws);
   if (p->blob) (void)hipFree(p->blob);
+  if (p->d_itemsU) (void)hipFree(p->d_itemsU);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   delete p;
 }
@@ -345,7 +365,7 @@ psatd_status psatd_set_workspace(psatd_plan_t p, void* dev, int64_t bytes) {
 psatd_status psatd_step(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3]) {
   psatd_status r = check_step_args(p, E, B, J);
   if (r != PSATD_OK) return r;
-  return enqueue_step(p, E, B, J, p->stream);
+  return enqueue_step(p, E, B, J, p->stream, p->h.jmode == PSATD_J_DEPOSITED);
 }
 
 psatd_status psatd_run(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3],
@@ -365,7 +385,8 @@ psatd_status psatd_run(psatd_plan_t p, void* const E[3], void* const B[3], void*
     g.nsteps = nsteps;
     HIPCHK(p, hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed));
     psatd_status er = PSATD_OK;
-    for (int i = 0; i < nsteps && er == PSATD_OK; ++i) er = enqueue_step(p, E, B, J, p->cap_stream);
+    for (int i = 0; i < nsteps && er == PSATD_OK; ++i)
+      er = enqueue_step(p, E, B, J, p->cap_stream, i == 0 && p->h.jmode == PSATD_J_DEPOSITED);
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
     if (er != PSATD_OK) {
@@ -391,26 +412,36 @@ psatd_status psatd_run_profiled(psatd_plan_t p, void* const E[3], void* const B[
   psatd_status r = check_step_args(p, E, B, J);
   if (r != PSATD_OK) return r;
   if (nsteps < 1 || !phase_ms) return fail(p, PSATD_E_INVALID, "nsteps < 1 or null phase_ms");
-  hipEvent_t ev[kNumPhases + 1];
-  for (int i = 0; i <= kNumPhases; ++i) HIPCHK(p, hipEventCreate(&ev[i]));
-  double acc[kNumPhases] = {0, 0, 0, 0, 0};
+  const size_t npairs = 2 + 3 * p->h.batches.size();
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev(npairs);
   psatd_status out = PSATD_OK;
-  for (int st = 0; st < nsteps && out == PSATD_OK; ++st) {
-    for (int ph = 0; ph < kNumPhases && out == PSATD_OK; ++ph) {
-      hipError_t e = hipEventRecord(ev[ph], p->stream);
-      if (e != hipSuccess) { out = fail(p, PSATD_E_HIP, "hipEventRecord"); break; }
-      out = enqueue_phase(p, ph, E, B, J, p->stream);
-    }
-    if (out != PSATD_OK) break;
-    if (hipEventRecord(ev[kNumPhases], p->stream) != hipSuccess) { out = fail(p, PSATD_E_HIP, "hipEventRecord"); break; }
-    if (hipEventSynchronize(ev[kNumPhases]) != hipSuccess) { out = fail(p, PSATD_E_HIP, "hipEventSynchronize"); break; }
-    for (int ph = 0; ph < kNumPhases; ++ph) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, ev[ph], ev[ph + 1]) != hipSuccess) { out = fail(p, PSATD_E_HIP, "hipEventElapsedTime"); break; }
-      acc[ph] += ms;
+  size_t made = 0;
+  for (; made < npairs; ++made) {
+    if (hipEventCreate(&ev[made].second.first) != hipSuccess) { out = fail(p, PSATD_E_HIP, "hipEventCreate"); break; }
+    if (hipEventCreate(&ev[made].second.second) != hipSuccess) {
+      (void)hipEventDestroy(ev[made].second.first);
+      out = fail(p, PSATD_E_HIP, "hipEventCreate");
+      break;
     }
   }
-  for (int i = 0; i <= kNumPhases; ++i) (void)hipEventDestroy(ev[i]);
+  double acc[kNumPhases] = {0, 0, 0, 0, 0};
+  for (int stp = 0; stp < nsteps && out == PSATD_OK; ++stp) {
+    out = enqueue_step(p, E, B, J, p->stream, stp == 0 && p->h.jmode == PSATD_J_DEPOSITED, &ev);
+    if (out != PSATD_OK) break;
+    if (hipEventSynchronize(ev[npairs - 1].second.second) != hipSuccess) { out = fail(p, PSATD_E_HIP, "hipEventSynchronize"); break; }
+    for (size_t i = 0; i < npairs; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[i].second.first, ev[i].second.second) != hipSuccess) {
+        out = fail(p, PSATD_E_HIP, "hipEventElapsedTime");
+        break;
+      }
+      acc[ev[i].first] += ms;
+    }
+  }
+  for (size_t i = 0; i < made; ++i) {
+    (void)hipEventDestroy(ev[i].second.first);
+    (void)hipEventDestroy(ev[i].second.second);
+  }
   if (out != PSATD_OK) return out;
   for (int ph = 0; ph < kNumPhases; ++ph) phase_ms[ph] = acc[ph] / nsteps;
   return PSATD_OK;
@@ -442,6 +473,56 @@ psatd_status psatd_modified_k(psatd_plan_t p, int32_t s, int32_t axis, double* o
   const int off = axis == 0 ? b.kx : (axis == 1 ? b.ky : b.kz);
   HIPCHK(p, hipStreamSynchronize(p->stream));
   HIPCHK(p, hipMemcpy(out, p->dp.kmod + off, (size_t)len * 8, hipMemcpyDeviceToHost));
+  return PSATD_OK;
+}
+
+psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
+  if (!p) return fail(nullptr, PSATD_E_INVALID, "null plan");
+  if (key < 0 || key >= PSATD_NTUNE) return fail(p, PSATD_E_INVALID, "unknown tuning key");
+  DevPlan& d = p->dp;
+  switch (key) {
+    case PSATD_TUNE_Z_PENCILS: {
+      if (value != 2 && value != 4 && value != 8 && value != 16)
+        return fail(p, PSATD_E_INVALID, "z pencils must be 2, 4, 8 or 16");
+      const int csz = (int)(2 * real_size(p->h.prec));
+      if ((int64_t)max_padded_z(p->h) * (9 * value + 1) * csz > kMaxDynLds)
+        return fail(p, PSATD_E_INVALID, "z tile does not fit the LDS");
+      HIPCHK(p, hipStreamSynchronize(p->stream));
+      set_z_tile(p->h, value);
+      HIPCHK(p, hipMemcpy(p->d_itemsU, p->h.itemsU.data(), p->h.itemsU.size() * 4, hipMemcpyHostToDevice));
+      HIPCHK(p, prepare_kernels(d.f64, p->h.ldsF, p->h.ldsI, p->h.ldsU));
+      d.PB = p->h.PB;
+      d.ldsU = p->h.ldsU;
+      d.nU = p->h.itemsU.back();
+      break;
+    }
+    case PSATD_TUNE_BATCH_BOXES: {
+      if (value < 0) return fail(p, PSATD_E_INVALID, "boxes per batch must be >= 0");
+      HIPCHK(p, hipStreamSynchronize(p->stream));
+      set_batches(p->h, value);
+      d.slab = p->h.batch_slab;
+      break;
+    }
+    case PSATD_TUNE_XCD_REMAP:
+      if (value != 0 && value != 1) return fail(p, PSATD_E_INVALID, "xcd remap must be 0 or 1");
+      d.xcd = value;
+      break;
+    default: {
+      if (value < 0) return fail(p, PSATD_E_INVALID, "grid size must be >= 0");
+      static const int phase_of[] = {0, 0, kPhaseFwd, kPhaseUpd, kPhaseInv, kPhaseExchEB, 0};
+      d.grid_cap[phase_of[key]] = value;
+      if (key == PSATD_TUNE_GRID_EXCH) d.grid_cap[kPhaseExchJ] = value;
+    }
+  }
+  p->tune[key] = value;
+  drop_graphs(p);
+  return PSATD_OK;
+}
+
+psatd_status psatd_get_tuning(psatd_plan_t p, int32_t key, int32_t* value) {
+  if (!p || !value) return fail(p, PSATD_E_INVALID, "null argument");
+  if (key < 0 || key >= PSATD_NTUNE) return fail(p, PSATD_E_INVALID, "unknown tuning key");
+  *value = p->tune[key];
   return PSATD_OK;
 }
 

@@ -13,11 +13,6 @@ namespace psatd {
 
 // Launch shapes (gfx950: 64-wide waves, 160 KiB LDS per compute unit).
 constexpr int kThreadsXY = 256;   // x/y plane passes, exchange, scatter/gather
-constexpr int kThreadsU32 = 512;  // z-update, FP32
-constexpr int kThreadsU64 = 256;  // z-update, FP64
-constexpr int kPB32 = 16;         // z-pencils per z-update work-group (128 B rows), FP32
-constexpr int kPB64 = 8;          // same, FP64
-constexpr int kMaxPPT = 6;        // k-points per thread held in registers by the z-update
 constexpr int kMaxDynLds = 160 * 1024;
 
 // One padded subdomain (Sec. 3.2, Fig. 2a).  Axes (x, y, z).
@@ -36,6 +31,14 @@ struct BoxD {
   int32_t pad_;
   int64_t foff;    // element offset of the box in a field buffer
   int64_t soff;    // complex-element offset of the box in one spectral field slab
+};
+
+// A batch of boxes [b0, b1) for the FFT/update passes: its work-item ranges
+// and the spectral offset of box b0 (the workspace holds the batch only).
+struct Batch {
+  int32_t b0, b1;
+  int32_t F0, nF, U0, nU, I0, nI;
+  int64_t sbias;
 };
 
 // Work list: item -> box by binary search in a prefix array (size nsub + 1).
@@ -60,9 +63,27 @@ struct Tables {
   int32_t nsub;
   const FftPlanD* plans;
   const cx<T>* tw;        // twiddle tables (forward sign)
-  const int32_t* idx;     // pos / ipos tables
   const double* kmod;     // modified wavenumbers (FP64)
 };
+
+// Copies total elements i -> dst(i, src(i)) with U loads in flight per
+// thread (all U loads are issued before the first store).
+template <int U, typename V, class Src, class Dst>
+PSATD_HD void copy_batched(int total, int tid, int nt, Src src, Dst dst) {
+  for (int base = tid; base < total; base += U * nt) {
+    V v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * nt;
+      if (i < total) v[u] = src(i);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * nt;
+      if (i < total) dst(i, v[u]);
+    }
+  }
+}
 
 // ------------------------------------------------------------------ pass F
 // Forward R2C along x and C2C along y of one z-plane of one field of one box.
@@ -75,8 +96,11 @@ struct FwdArgs {
   const T* in[9];
   cx<T>* spec;             // spectral slabs, field f at spec + f * slab
   int64_t slab;
+  int64_t sbias;           // spectral offset of the first box held by spec
 };
 
+// LDS: the plane [y][x] with row stride ld, then the twiddles of the x plan
+// (Nh), the y plan (Py) and W_Px (real <-> half spectrum).
 template <typename T, class Bar>
 PSATD_HD void body_fwd_xy(const FwdArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar) {
   const int s = find_box(a.items, a.t.nsub, item);
@@ -88,32 +112,50 @@ PSATD_HD void body_fwd_xy(const FwdArgs<T>& a, int item, int tid, int nt, cx<T>*
   const int Nh = Px >> 1, H = bx.H, ld = bx.ld;
   const FftPlanD* plx = a.t.plans + bx.planx;
   const FftPlanD* ply = a.t.plans + bx.plany;
-  const int32_t* posx = a.t.idx + plx->pos;
-  const int32_t* posy = a.t.idx + ply->pos;
+  cx<T>* twx = lds + Py * ld;
+  cx<T>* twy = twx + Nh;
+  cx<T>* twr = twy + Py;
+  const cx<T>* gtx = a.t.tw + plx->tw;
+  const cx<T>* gty = a.t.tw + ply->tw;
+  const cx<T>* gtr = a.t.tw + bx.twr;
 
-  // packed real rows -> LDS rows in stage-digit order (for the dit transform)
+  // packed real rows (x natural) -> LDS rows in stage-digit order along x,
+  // together with the three twiddle tables
   const cx<T>* src = reinterpret_cast<const cx<T>*>(a.in[f] + bx.foff + (int64_t)z * Py * Px);
-  for (int i = tid; i < Py * Nh; i += nt) {
-    const int y = i / Nh;
-    const int nn = i - y * Nh;
-    lds[y * ld + posx[nn]] = src[i];
-  }
+  const int nplane = Py * Nh;
+  const FastDiv dNh = make_fastdiv((uint32_t)Nh);
+  copy_batched<8, cx<T>>(nplane + Nh + Py + Px, tid, nt,
+                         [&](int i) {
+                           if (i < nplane) return src[i];
+                           const int j = i - nplane;
+                           return j < Nh ? gtx[j] : (j < Nh + Py ? gty[j - Nh] : gtr[j - Nh - Py]);
+                         },
+                         [&](int i, cx<T> v) {
+                           if (i < nplane) {
+                             const int y = (int)fdiv((uint32_t)i, dNh);
+                             lds[y * ld + plan_pos(plx, i - y * Nh)] = v;
+                           } else {
+                             twx[i - nplane] = v;  // twx, twy, twr are contiguous
+                           }
+                         });
   bar();
-  fft_dit<-1>(lds, Py, ld, 1, plx, a.t.tw, tid, nt, bar);
-  const cx<T>* twr = a.t.tw + bx.twr;
+  fft_dit<-1>(lds, Py, ld, 1, plx, twx, tid, nt, bar);
   const int np = Nh / 2 + 1;
+  const FastDiv dnp = make_fastdiv((uint32_t)np);
   for (int i = tid; i < Py * np; i += nt) {
-    const int y = i / np;
+    const int y = (int)fdiv((uint32_t)i, dnp);
     r2c_post(lds + y * ld, i - y * np, Nh, twr);
   }
   bar();
-  fft_dif<-1>(lds, H, 1, ld, ply, a.t.tw, tid, nt, bar);
-  cx<T>* dst = a.spec + f * a.slab + bx.soff + (int64_t)z * Py * H;
-  for (int i = tid; i < Py * H; i += nt) {
-    const int ky = i / H;
-    const int kx = i - ky * H;
-    dst[i] = lds[posy[ky] * ld + kx];
-  }
+  fft_dif<-1>(lds, H, 1, ld, ply, twy, tid, nt, bar);
+  cx<T>* dst = a.spec + f * a.slab + (bx.soff - a.sbias) + (int64_t)z * Py * H;
+  const FastDiv dH = make_fastdiv((uint32_t)H);
+  copy_batched<8, cx<T>>(Py * H, tid, nt,
+                         [&](int i) {
+                           const int ky = (int)fdiv((uint32_t)i, dH);
+                           return lds[plan_pos(ply, ky) * ld + (i - ky * H)];
+                         },
+                         [&](int i, cx<T> v) { dst[i] = v; });
 }
 
 // ------------------------------------------------------------------ pass U
@@ -193,10 +235,15 @@ struct UpdArgs {
   const int32_t* items;  // prefix over boxes of ceil(P[1] H / PB)
   cx<T>* spec;
   int64_t slab;
+  int64_t sbias;
   UpdConst k;
 };
 
-template <typename T, int PB, int PPT, class Bar>
+// The 9 fields of PB consecutive (ky, kx) pencils are staged in LDS as
+// [z][f * PB + p] (W = 9 PB complex per z row), so that all 9 (then the 6
+// output) fields are transformed by one multi-transform pass with a uniform
+// element stride W.  Pencils past the end of the box (last block) are zeros.
+template <typename T, int PB, class Bar>
 PSATD_HD void body_z_update(const UpdArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar) {
   const int s = find_box(a.items, a.t.nsub, item);
   const BoxD& bx = a.t.box[s];
@@ -206,76 +253,81 @@ PSATD_HD void body_z_update(const UpdArgs<T>& a, int item, int tid, int nt, cx<T
   const int q0 = blk * PB;
   const int np = (nq - q0) < PB ? (nq - q0) : PB;
   const FftPlanD* plz = a.t.plans + bx.planz;
-  const int32_t* iposz = a.t.idx + plz->ipos;
-  const int tot = Pz * PB;
+  constexpr int W = 9 * PB;
+  cx<T>* twz = lds + Pz * W;
+  const cx<T>* gtz = a.t.tw + plz->tw;
+  const cx<T>* src = a.spec + (bx.soff - a.sbias) + q0;
+  const int64_t slab = a.slab;
+  const FastDiv dPz = make_fastdiv((uint32_t)Pz);
+  const int ndata = 9 * Pz * PB;
 
-  // 9 field values of each owned k-point, split re/im so they stay in VGPRs
-  T rr[PPT][9], ri[PPT][9];
-  for (int f = 0; f < 9; ++f) {
-    const cx<T>* src = a.spec + f * a.slab + bx.soff + q0;
-    for (int i = tid; i < tot; i += nt) {
-      const int z = i / PB;
-      const int p = i - z * PB;
-      if (p < np) lds[i] = src[(int64_t)z * nq + p];
-    }
-    bar();
-    fft_dif<-1>(lds, np, 1, PB, plz, a.t.tw, tid, nt, bar);
-#pragma unroll
-    for (int r = 0; r < PPT; ++r) {
-      const int i = tid + r * nt;
-      if (i < tot) {
-        const cx<T> v = lds[i];
-        // f is uniform: a select chain keeps every register slot static
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-          rr[r][k] = (f == k) ? v.x : rr[r][k];
-          ri[r][k] = (f == k) ? v.y : ri[r][k];
+  copy_batched<8, cx<T>>(ndata + Pz, tid, nt,
+      [&](int i) {
+        if (i >= ndata) return gtz[i - ndata];
+        const int p = i % PB;
+        const int r = i / PB;
+        const int f = (int)fdiv((uint32_t)r, dPz);
+        const int z = r - f * Pz;
+        return (p < np) ? src[f * slab + (int64_t)z * nq + p] : cx<T>{T(0), T(0)};
+      },
+      [&](int i, cx<T> v) {
+        if (i >= ndata) {
+          twz[i - ndata] = v;
+          return;
         }
-      }
-    }
-    bar();
-  }
+        const int p = i % PB;
+        const int r = i / PB;
+        const int f = (int)fdiv((uint32_t)r, dPz);
+        const int z = r - f * Pz;
+        lds[z * W + f * PB + p] = v;
+      });
+  bar();
+  fft_dif<-1>(lds, 9 * PB, 1, W, plz, twz, tid, nt, bar);
+
   const double* kxt = a.t.kmod + bx.kx;
   const double* kyt = a.t.kmod + bx.ky;
   const double* kzt = a.t.kmod + bx.kz;
+  const FastDiv dH = make_fastdiv((uint32_t)H);
+  for (int i = tid; i < Pz * PB; i += nt) {
+    const int slot = i / PB;
+    const int p = i % PB;
+    if (p >= np) continue;
+    cx<T>* row = lds + slot * W + p;
+    T vr[9], vi[9];
 #pragma unroll
-  for (int r = 0; r < PPT; ++r) {
-    const int i = tid + r * nt;
-    if (i < tot) {
-      const int slot = i / PB;
-      const int p = i - slot * PB;
-      if (p < np) {
-        const int q = q0 + p;
-        const int ky = q / H;
-        const int kx = q - ky * H;
-        psatd_point(rr[r], ri[r], kxt[kx], kyt[ky], kzt[iposz[slot]], a.k.c, a.k.dt);
-      }
+    for (int f = 0; f < 9; ++f) {
+      const cx<T> v = row[f * PB];
+      vr[f] = v.x;
+      vi[f] = v.y;
     }
+    const int q = q0 + p;
+    const int ky = (int)fdiv((uint32_t)q, dH);
+    const int kx = q - ky * H;
+    psatd_point(vr, vi, kxt[kx], kyt[ky], kzt[plan_index(plz, slot)], a.k.c, a.k.dt);
+#pragma unroll
+    for (int f = 0; f < 6; ++f) row[f * PB] = cx<T>{vr[f], vi[f]};
   }
-  for (int f = 0; f < 6; ++f) {
-#pragma unroll
-    for (int r = 0; r < PPT; ++r) {
-      const int i = tid + r * nt;
-      if (i < tot) {
-        cx<T> v = {rr[r][0], ri[r][0]};
-#pragma unroll
-        for (int k = 1; k < 6; ++k) {
-          v.x = (f == k) ? rr[r][k] : v.x;
-          v.y = (f == k) ? ri[r][k] : v.y;
+  bar();
+  fft_dit<+1>(lds, 6 * PB, 1, W, plz, twz, tid, nt, bar);
+
+  cx<T>* dst = a.spec + (bx.soff - a.sbias) + q0;
+  copy_batched<8, cx<T>>(6 * Pz * PB, tid, nt,
+      [&](int i) {
+        const int p = i % PB;
+        const int r = i / PB;
+        const int f = (int)fdiv((uint32_t)r, dPz);
+        const int z = r - f * Pz;
+        return lds[z * W + f * PB + p];
+      },
+      [&](int i, cx<T> v) {
+        const int p = i % PB;
+        if (p < np) {
+          const int r = i / PB;
+          const int f = (int)fdiv((uint32_t)r, dPz);
+          const int z = r - f * Pz;
+          dst[f * slab + (int64_t)z * nq + p] = v;
         }
-        lds[i] = v;
-      }
-    }
-    bar();
-    fft_dit<+1>(lds, np, 1, PB, plz, a.t.tw, tid, nt, bar);
-    cx<T>* dst = a.spec + f * a.slab + bx.soff + q0;
-    for (int i = tid; i < tot; i += nt) {
-      const int z = i / PB;
-      const int p = i - z * PB;
-      if (p < np) dst[(int64_t)z * nq + p] = lds[i];
-    }
-    bar();
-  }
+      });
 }
 
 // ------------------------------------------------------------------ pass I
@@ -287,9 +339,12 @@ struct InvArgs {
   const int32_t* items;  // prefix over boxes of n[2] * 6
   const cx<T>* spec;
   int64_t slab;
+  int64_t sbias;
   T* out[6];
 };
 
+// LDS: the plane with row stride ld, then the twiddles of the y plan (Py),
+// the x plan (Nh) and W_Px.
 template <typename T, class Bar>
 PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar) {
   const int s = find_box(a.items, a.t.nsub, item);
@@ -302,36 +357,59 @@ PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>*
   const int Nh = Px >> 1, H = bx.H, ld = bx.ld;
   const FftPlanD* plx = a.t.plans + bx.planx;
   const FftPlanD* ply = a.t.plans + bx.plany;
-  const int32_t* posx = a.t.idx + plx->pos;
-  const int32_t* posy = a.t.idx + ply->pos;
+  cx<T>* twy = lds + Py * ld;
+  cx<T>* twx = twy + Py;
+  cx<T>* twr = twx + Nh;
+  const cx<T>* gty = a.t.tw + ply->tw;
+  const cx<T>* gtx = a.t.tw + plx->tw;
+  const cx<T>* gtr = a.t.tw + bx.twr;
 
-  const cx<T>* src = a.spec + f * a.slab + bx.soff + (int64_t)z * Py * H;
-  for (int i = tid; i < Py * H; i += nt) {
-    const int ky = i / H;
-    const int kx = i - ky * H;
-    lds[posy[ky] * ld + kx] = src[i];
-  }
+  // half-spectrum rows (ky natural) -> LDS rows in stage-digit order along y
+  const cx<T>* src = a.spec + f * a.slab + (bx.soff - a.sbias) + (int64_t)z * Py * H;
+  const int nplane = Py * H;
+  const FastDiv dH = make_fastdiv((uint32_t)H);
+  copy_batched<8, cx<T>>(nplane + Py + Nh + Px, tid, nt,
+                         [&](int i) {
+                           if (i < nplane) return src[i];
+                           const int j = i - nplane;
+                           return j < Py ? gty[j] : (j < Py + Nh ? gtx[j - Py] : gtr[j - Py - Nh]);
+                         },
+                         [&](int i, cx<T> v) {
+                           if (i < nplane) {
+                             const int ky = (int)fdiv((uint32_t)i, dH);
+                             lds[plan_pos(ply, ky) * ld + (i - ky * H)] = v;
+                           } else {
+                             twy[i - nplane] = v;  // twy, twx, twr are contiguous
+                           }
+                         });
   bar();
-  fft_dit<+1>(lds, H, 1, ld, ply, a.t.tw, tid, nt, bar);
+  fft_dit<+1>(lds, H, 1, ld, ply, twy, tid, nt, bar);
   const int ny = bx.n[1], gy = bx.g[1];
-  const cx<T>* twr = a.t.tw + bx.twr;
   const int np = Nh / 2 + 1;
+  const FastDiv dnp = make_fastdiv((uint32_t)np);
   for (int i = tid; i < ny * np; i += nt) {
-    const int y = i / np;
+    const int y = (int)fdiv((uint32_t)i, dnp);
     c2r_pre(lds + (gy + y) * ld, i - y * np, Nh, twr);
   }
   bar();
-  fft_dif<+1>(lds + gy * ld, ny, ld, 1, plx, a.t.tw, tid, nt, bar);
-  const T sc = T(1.0 / ((double)Px * (double)Py * (double)Pz));
+  fft_dif<+1>(lds + gy * ld, ny, ld, 1, plx, twx, tid, nt, bar);
+  // 1/V applied in FP64 and rounded once: an FP32 1/V (not a power of two for
+  // most V) would bias every step by the same relative amount.
+  const double sc = 1.0 / ((double)Px * (double)Py * (double)Pz);
   const int nx = bx.n[0], gx = bx.g[0];
   T* dst = a.out[f] + bx.foff + (int64_t)z * Py * Px;
-  for (int i = tid; i < ny * nx; i += nt) {
-    const int yy = i / nx;
-    const int x = gx + (i - yy * nx);
-    const int y = gy + yy;
-    const cx<T> v = lds[y * ld + posx[x >> 1]];
-    dst[y * Px + x] = ((x & 1) ? v.y : v.x) * sc;
-  }
+  const FastDiv dnx = make_fastdiv((uint32_t)nx);
+  copy_batched<8, T>(ny * nx, tid, nt,
+                     [&](int i) {
+                       const int yy = (int)fdiv((uint32_t)i, dnx);
+                       const int x = gx + (i - yy * nx);
+                       const cx<T> v = lds[(gy + yy) * ld + plan_pos(plx, x >> 1)];
+                       return (T)((double)((x & 1) ? v.y : v.x) * sc);
+                     },
+                     [&](int i, T v) {
+                       const int yy = (int)fdiv((uint32_t)i, dnx);
+                       dst[(gy + yy) * Px + gx + (i - yy * nx)] = v;
+                     });
 }
 
 // --------------------------------------------------------------- exchange
@@ -368,22 +446,40 @@ PSATD_HD void body_fill(const FillArgs<T>& a, int item, int tid, int nt) {
   const int Px = bx.P[0], Py = bx.P[1];
   const bool zg = z < bx.g[2] || z >= bx.g[2] + bx.n[2];
   const int Z = pmod(bx.lo[2] - bx.g[2] + z, a.own.N[2]);
-  // interior rows only have guard cells at both x ends
   const int gx = bx.g[0], nx = bx.n[0];
-  for (int i = tid; i < Py * Px; i += nt) {
-    const int y = i / Px;
-    const int x = i - y * Px;
-    const bool yg = y < bx.g[1] || y >= bx.g[1] + bx.n[1];
-    const bool xg = x < gx || x >= gx + nx;
-    if (!(zg || yg || xg)) continue;
-    const int Y = pmod(bx.lo[1] - bx.g[1] + y, a.own.N[1]);
-    const int X = pmod(bx.lo[0] - gx + x, a.own.N[0]);
-    const int o = owner_of(a.own, X, Y, Z);
-    const BoxD& bo = a.box[o];
-    const int64_t src = bo.foff + ((int64_t)(Z - bo.lo[2] + bo.g[2]) * bo.P[1] + (Y - bo.lo[1] + bo.g[1])) * bo.P[0] +
-                        (X - bo.lo[0] + bo.g[0]);
-    const int64_t dst = bx.foff + ((int64_t)z * Py + y) * Px + x;
-    for (int c = 0; c < a.ncomp; ++c) a.comp[c][dst] = a.comp[c][src];
+  const int64_t rowbase = bx.foff + (int64_t)z * Py * Px;
+  constexpr int U = 4;
+  for (int base = tid; base < Py * Px; base += U * nt) {
+    int64_t src[U], dst[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * nt;
+      ok[u] = false;
+      src[u] = dst[u] = 0;
+      if (i >= Py * Px) continue;
+      const int y = i / Px;
+      const int x = i - y * Px;
+      const bool yg = y < bx.g[1] || y >= bx.g[1] + bx.n[1];
+      const bool xg = x < gx || x >= gx + nx;
+      if (!(zg || yg || xg)) continue;  // interior cells are not touched
+      const int Y = pmod(bx.lo[1] - bx.g[1] + y, a.own.N[1]);
+      const int X = pmod(bx.lo[0] - gx + x, a.own.N[0]);
+      const BoxD& bo = a.box[owner_of(a.own, X, Y, Z)];
+      src[u] = bo.foff + ((int64_t)(Z - bo.lo[2] + bo.g[2]) * bo.P[1] + (Y - bo.lo[1] + bo.g[1])) * bo.P[0] +
+               (X - bo.lo[0] + bo.g[0]);
+      dst[u] = rowbase + i;
+      ok[u] = true;
+    }
+    for (int c = 0; c < a.ncomp; ++c) {
+      T v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (ok[u]) v[u] = a.comp[c][src[u]];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (ok[u]) a.comp[c][dst[u]] = v[u];
+    }
   }
 }
 

@@ -16,36 +16,49 @@ struct BlockBarrier {
 
 extern __shared__ __attribute__((aligned(16))) unsigned char psatd_lds[];
 
+// Work-groups are dispatched round-robin over the 8 XCDs; with remap, block
+// b of the first 8*floor(G/8) takes item (b % 8) * (G/8) + b / 8 so that
+// consecutive items (neighbouring memory) run on one XCD and share its L2.
+__device__ __forceinline__ int first_item(int remap) {
+  int b = blockIdx.x;
+  const int G = gridDim.x;
+  if (remap && G >= 8) {
+    const int full = G & ~7;
+    if (b < full) b = (b & 7) * (full >> 3) + (b >> 3);
+  }
+  return b;
+}
+
 template <typename T>
-__global__ __launch_bounds__(kThreadsXY) void k_fwd_xy(FwdArgs<T> a, int nitems) {
+__global__ __launch_bounds__(kThreadsXY) void k_fwd_xy(FwdArgs<T> a, int item0, int nitems, int remap) {
   cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
-  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
-    body_fwd_xy(a, item, threadIdx.x, blockDim.x, lds, BlockBarrier{});
+  for (int it = first_item(remap); it < nitems; it += gridDim.x) {
+    body_fwd_xy(a, item0 + it, threadIdx.x, blockDim.x, lds, BlockBarrier{});
     __syncthreads();
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreadsXY) void k_inv_xy(InvArgs<T> a, int nitems) {
+__global__ __launch_bounds__(kThreadsXY) void k_inv_xy(InvArgs<T> a, int item0, int nitems, int remap) {
   cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
-  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
-    body_inv_xy(a, item, threadIdx.x, blockDim.x, lds, BlockBarrier{});
+  for (int it = first_item(remap); it < nitems; it += gridDim.x) {
+    body_inv_xy(a, item0 + it, threadIdx.x, blockDim.x, lds, BlockBarrier{});
     __syncthreads();
   }
 }
 
-template <typename T, int NT, int PB, int PPT>
-__global__ __launch_bounds__(NT) void k_z_update(UpdArgs<T> a, int nitems) {
+template <typename T, int NT, int PB>
+__global__ __launch_bounds__(NT) void k_z_update(UpdArgs<T> a, int item0, int nitems, int remap) {
   cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
-  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
-    body_z_update<T, PB, PPT>(a, item, threadIdx.x, NT, lds, BlockBarrier{});
+  for (int it = first_item(remap); it < nitems; it += gridDim.x) {
+    body_z_update<T, PB>(a, item0 + it, threadIdx.x, NT, lds, BlockBarrier{});
     __syncthreads();
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreadsXY) void k_fill(FillArgs<T> a, int nitems) {
-  for (int item = blockIdx.x; item < nitems; item += gridDim.x)
+__global__ __launch_bounds__(kThreadsXY) void k_fill(FillArgs<T> a, int nitems, int remap) {
+  for (int item = first_item(remap); item < nitems; item += gridDim.x)
     body_fill(a, item, threadIdx.x, blockDim.x);
 }
 
@@ -89,37 +102,34 @@ static Tables<T> tables(const DevPlan& p) {
   t.nsub = p.nsub;
   t.plans = p.plans;
   t.tw = reinterpret_cast<const cx<T>*>(p.tw);
-  t.idx = p.idx;
   t.kmod = p.kmod;
   return t;
 }
 
-template <typename T, int NT, int PB>
+template <typename T>
 static hipError_t set_upd_attr(int lds) {
-  hipError_t e = hipSuccess;
-  e = hipFuncSetAttribute((const void*)k_z_update<T, NT, PB, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_z_update<T, NT, PB, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_z_update<T, NT, PB, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_z_update<T, NT, PB, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_z_update<T, NT, PB, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_z_update<T, NT, PB, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  const void* fns[] = {
+      (const void*)k_z_update<T, 512, 2>,  (const void*)k_z_update<T, 512, 4>,
+      (const void*)k_z_update<T, 512, 8>,  (const void*)k_z_update<T, 512, 16>,
+      (const void*)k_z_update<T, 1024, 2>, (const void*)k_z_update<T, 1024, 4>,
+      (const void*)k_z_update<T, 1024, 8>, (const void*)k_z_update<T, 1024, 16>};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
-hipError_t prepare_kernels(bool f64, int ldsF, int ldsI, int ldsU, int /*PPT*/) {
+hipError_t prepare_kernels(bool f64, int ldsF, int ldsI, int ldsU) {
   hipError_t e;
   if (f64) {
     if ((e = hipFuncSetAttribute((const void*)k_fwd_xy<double>, hipFuncAttributeMaxDynamicSharedMemorySize, ldsF)) != hipSuccess) return e;
     if ((e = hipFuncSetAttribute((const void*)k_inv_xy<double>, hipFuncAttributeMaxDynamicSharedMemorySize, ldsI)) != hipSuccess) return e;
-    return set_upd_attr<double, kThreadsU64, kPB64>(ldsU);
+    return set_upd_attr<double>(ldsU);
   }
   if ((e = hipFuncSetAttribute((const void*)k_fwd_xy<float>, hipFuncAttributeMaxDynamicSharedMemorySize, ldsF)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)k_inv_xy<float>, hipFuncAttributeMaxDynamicSharedMemorySize, ldsI)) != hipSuccess) return e;
-  return set_upd_attr<float, kThreadsU32, kPB32>(ldsU);
+  return set_upd_attr<float>(ldsU);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -134,7 +144,7 @@ static hipError_t fill_t(const DevPlan& p, void* const* comps, int ncomp, hipStr
   for (int c = 0; c < 9; ++c) a.comp[c] = (c < ncomp) ? reinterpret_cast<T*>(comps[c]) : nullptr;
   const int g = grid_for(p.nP, p.grid_cap[kPhaseExchEB]);
   if (!g) return hipSuccess;
-  hipLaunchKernelGGL(k_fill<T>, dim3(g), dim3(kThreadsXY), 0, st, a, p.nP);
+  hipLaunchKernelGGL(k_fill<T>, dim3(g), dim3(kThreadsXY), 0, st, a, p.nP, p.xcd);
   return hipGetLastError();
 }
 
@@ -163,7 +173,7 @@ hipError_t launch_sum(const DevPlan& p, void* const* J, hipStream_t st) {
 }
 
 template <typename T>
-static hipError_t fwd_t(const DevPlan& p, void* const* in9, void* spec, hipStream_t st) {
+static hipError_t fwd_t(const DevPlan& p, const Batch& b, void* const* in9, void* spec, hipStream_t st) {
   FwdArgs<T> a;
   a.t = tables<T>(p);
   a.items = p.itemsF;
@@ -171,60 +181,66 @@ static hipError_t fwd_t(const DevPlan& p, void* const* in9, void* spec, hipStrea
   for (int f = 0; f < 9; ++f) a.in[f] = reinterpret_cast<const T*>(in9[f]);
   a.spec = reinterpret_cast<cx<T>*>(spec);
   a.slab = p.slab;
-  const int g = grid_for(p.nF, p.grid_cap[kPhaseFwd]);
+  a.sbias = b.sbias;
+  const int g = grid_for(b.nF, p.grid_cap[kPhaseFwd]);
   if (!g) return hipSuccess;
-  hipLaunchKernelGGL(k_fwd_xy<T>, dim3(g), dim3(kThreadsXY), p.ldsF, st, a, p.nF);
+  hipLaunchKernelGGL(k_fwd_xy<T>, dim3(g), dim3(kThreadsXY), p.ldsF, st, a, b.F0, b.nF, p.xcd);
   return hipGetLastError();
 }
 
-hipError_t launch_fwd(const DevPlan& p, void* const* in9, void* spec, hipStream_t st) {
-  return p.f64 ? fwd_t<double>(p, in9, spec, st) : fwd_t<float>(p, in9, spec, st);
+hipError_t launch_fwd(const DevPlan& p, const Batch& b, void* const* in9, void* spec, hipStream_t st) {
+  return p.f64 ? fwd_t<double>(p, b, in9, spec, st) : fwd_t<float>(p, b, in9, spec, st);
 }
 
 template <typename T, int NT, int PB>
-static hipError_t upd_t(const DevPlan& p, void* spec, hipStream_t st) {
+static hipError_t upd_launch(const DevPlan& p, const Batch& b, const UpdArgs<T>& a, int g, hipStream_t st) {
+  hipLaunchKernelGGL((k_z_update<T, NT, PB>), dim3(g), dim3(NT), p.ldsU, st, a, b.U0, b.nU, p.xcd);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t upd_t(const DevPlan& p, const Batch& b, void* spec, hipStream_t st) {
   UpdArgs<T> a;
   a.t = tables<T>(p);
   a.items = p.itemsU;
   a.spec = reinterpret_cast<cx<T>*>(spec);
   a.slab = p.slab;
+  a.sbias = b.sbias;
   a.k.c = p.c;
   a.k.dt = p.dt;
-  const int g = grid_for(p.nU, p.grid_cap[kPhaseUpd]);
+  const int g = grid_for(b.nU, p.grid_cap[kPhaseUpd]);
   if (!g) return hipSuccess;
-  switch (p.PPT) {
-    case 1: hipLaunchKernelGGL((k_z_update<T, NT, PB, 1>), dim3(g), dim3(NT), p.ldsU, st, a, p.nU); break;
-    case 2: hipLaunchKernelGGL((k_z_update<T, NT, PB, 2>), dim3(g), dim3(NT), p.ldsU, st, a, p.nU); break;
-    case 3: hipLaunchKernelGGL((k_z_update<T, NT, PB, 3>), dim3(g), dim3(NT), p.ldsU, st, a, p.nU); break;
-    case 4: hipLaunchKernelGGL((k_z_update<T, NT, PB, 4>), dim3(g), dim3(NT), p.ldsU, st, a, p.nU); break;
-    case 5: hipLaunchKernelGGL((k_z_update<T, NT, PB, 5>), dim3(g), dim3(NT), p.ldsU, st, a, p.nU); break;
-    case 6: hipLaunchKernelGGL((k_z_update<T, NT, PB, 6>), dim3(g), dim3(NT), p.ldsU, st, a, p.nU); break;
+  const bool big = p.NTU == 1024;
+  switch (p.PB) {
+    case 2: return big ? upd_launch<T, 1024, 2>(p, b, a, g, st) : upd_launch<T, 512, 2>(p, b, a, g, st);
+    case 4: return big ? upd_launch<T, 1024, 4>(p, b, a, g, st) : upd_launch<T, 512, 4>(p, b, a, g, st);
+    case 8: return big ? upd_launch<T, 1024, 8>(p, b, a, g, st) : upd_launch<T, 512, 8>(p, b, a, g, st);
+    case 16: return big ? upd_launch<T, 1024, 16>(p, b, a, g, st) : upd_launch<T, 512, 16>(p, b, a, g, st);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
-hipError_t launch_upd(const DevPlan& p, void* spec, hipStream_t st) {
-  return p.f64 ? upd_t<double, kThreadsU64, kPB64>(p, spec, st)
-               : upd_t<float, kThreadsU32, kPB32>(p, spec, st);
+hipError_t launch_upd(const DevPlan& p, const Batch& b, void* spec, hipStream_t st) {
+  return p.f64 ? upd_t<double>(p, b, spec, st) : upd_t<float>(p, b, spec, st);
 }
 
 template <typename T>
-static hipError_t inv_t(const DevPlan& p, const void* spec, void* const* out6, hipStream_t st) {
+static hipError_t inv_t(const DevPlan& p, const Batch& b, const void* spec, void* const* out6, hipStream_t st) {
   InvArgs<T> a;
   a.t = tables<T>(p);
   a.items = p.itemsI;
   a.spec = reinterpret_cast<const cx<T>*>(spec);
   a.slab = p.slab;
+  a.sbias = b.sbias;
   for (int f = 0; f < 6; ++f) a.out[f] = reinterpret_cast<T*>(out6[f]);
-  const int g = grid_for(p.nI, p.grid_cap[kPhaseInv]);
+  const int g = grid_for(b.nI, p.grid_cap[kPhaseInv]);
   if (!g) return hipSuccess;
-  hipLaunchKernelGGL(k_inv_xy<T>, dim3(g), dim3(kThreadsXY), p.ldsI, st, a, p.nI);
+  hipLaunchKernelGGL(k_inv_xy<T>, dim3(g), dim3(kThreadsXY), p.ldsI, st, a, b.I0, b.nI, p.xcd);
   return hipGetLastError();
 }
 
-hipError_t launch_inv(const DevPlan& p, const void* spec, void* const* out6, hipStream_t st) {
-  return p.f64 ? inv_t<double>(p, spec, out6, st) : inv_t<float>(p, spec, out6, st);
+hipError_t launch_inv(const DevPlan& p, const Batch& b, const void* spec, void* const* out6, hipStream_t st) {
+  return p.f64 ? inv_t<double>(p, b, spec, out6, st) : inv_t<float>(p, b, spec, out6, st);
 }
 
 template <typename T>

@@ -16,7 +16,6 @@ struct DevPlan {
   const BoxD* box;
   const FftPlanD* plans;
   const void* tw;           // cx<double> or cx<float> twiddles
-  const int32_t* idx;
   const double* kmod;
   OwnerD own;
   const int32_t* nbr_off;
@@ -28,7 +27,8 @@ struct DevPlan {
   const int32_t* itemsN;    // n[2]
   int32_t nF, nU, nI, nP, nN;
   int32_t ldsF, ldsI, ldsU;  // dynamic LDS bytes per work-group
-  int32_t PB, PPT;           // pencils per z-update work-group, points per thread
+  int32_t PB, NTU;           // pencils per z-update work-group, its thread count
+  int32_t xcd;               // 1: consecutive items on the same XCD (L2 sharing)
   int64_t slab;              // complex elements of one spectral field slab
   double c, dt;
   int32_t grid_cap[kNumPhases];  // 0: one work-group per item; else persistent grid
@@ -36,14 +36,14 @@ struct DevPlan {
 
 hipError_t launch_fill(const DevPlan& p, void* const* comps, int ncomp, hipStream_t st);
 hipError_t launch_sum(const DevPlan& p, void* const* J, hipStream_t st);
-hipError_t launch_fwd(const DevPlan& p, void* const* in9, void* spec, hipStream_t st);
-hipError_t launch_upd(const DevPlan& p, void* spec, hipStream_t st);
-hipError_t launch_inv(const DevPlan& p, const void* spec, void* const* out6, hipStream_t st);
+hipError_t launch_fwd(const DevPlan& p, const Batch& b, void* const* in9, void* spec, hipStream_t st);
+hipError_t launch_upd(const DevPlan& p, const Batch& b, void* spec, hipStream_t st);
+hipError_t launch_inv(const DevPlan& p, const Batch& b, const void* spec, void* const* out6, hipStream_t st);
 hipError_t launch_scatter(const DevPlan& p, const void* const* glob, void* const* pad, hipStream_t st);
 hipError_t launch_gather(const DevPlan& p, const void* const* pad, void* const* glob, hipStream_t st);
 hipError_t launch_modk(const KEntry* entries, int nent, int maxN, int order_p, double* kmod,
                        hipStream_t st);
-hipError_t prepare_kernels(bool f64, int ldsF, int ldsI, int ldsU, int PPT);
+hipError_t prepare_kernels(bool f64, int ldsF, int ldsI, int ldsU);
 
 
 }  // namespace psatd

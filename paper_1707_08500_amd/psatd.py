@@ -23,6 +23,8 @@ PRECISIONS = {"f64": F64, "f32": F32_VALU, "f32_valu": F32_VALU,
               "bf16x3": F32_BF16X3, "bf16x6": F32_BF16X6}
 JMODES = {"replicated": J_REPLICATED, "deposited": J_DEPOSITED}
 PHASES = ("exchange_J", "fft_xy_fwd", "z_update", "fft_xy_inv", "exchange_EB")
+TUNING = {"z_pencils": 0, "xcd_remap": 1, "grid_fwd": 2, "grid_upd": 3, "grid_inv": 4,
+          "grid_exch": 5, "batch_boxes": 6}
 NPHASES = len(PHASES)
 
 STATUS = {0: "PSATD_OK", 1: "PSATD_E_INVALID", 2: "PSATD_E_NOMEM", 3: "PSATD_E_HIP",
@@ -31,7 +33,7 @@ STATUS = {0: "PSATD_OK", 1: "PSATD_E_INVALID", 2: "PSATD_E_NOMEM", 3: "PSATD_E_H
 SYMBOLS = ("psatd_plan", "psatd_validate", "psatd_field_elems", "psatd_field_layout",
            "psatd_workspace_bytes", "psatd_set_workspace", "psatd_step", "psatd_run",
            "psatd_run_profiled", "psatd_scatter", "psatd_gather", "psatd_modified_k",
-           "psatd_set_stream", "psatd_sync", "psatd_destroy", "psatd_status_string",
+           "psatd_set_tuning", "psatd_get_tuning", "psatd_set_stream", "psatd_sync", "psatd_destroy", "psatd_status_string",
            "psatd_last_error", "psatd_version")
 
 
@@ -64,6 +66,8 @@ def _load():
         "psatd_scatter": ([P, VPP, VPP], i32),
         "psatd_gather": ([P, VPP, VPP], i32),
         "psatd_modified_k": ([P, i32, i32, DP, i64], i32),
+        "psatd_set_tuning": ([P, i32, i32], i32),
+        "psatd_get_tuning": ([P, i32, I32P], i32),
         "psatd_set_stream": ([P, P], i32),
         "psatd_sync": ([P], i32),
         "psatd_destroy": ([P], None),
@@ -193,6 +197,18 @@ class Plan:
         _check(LIB.psatd_modified_k(self._h, int(s), int(axis),
                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                     int(pn[axis])), self._h)
+        return out
+
+    def set_tuning(self, **kw):
+        for k, v in kw.items():
+            _check(LIB.psatd_set_tuning(self._h, TUNING[k], int(v)), self._h)
+
+    def tuning(self):
+        out = {}
+        for k, key in TUNING.items():
+            v = ctypes.c_int32(0)
+            _check(LIB.psatd_get_tuning(self._h, key, ctypes.byref(v)), self._h)
+            out[k] = v.value
         return out
 
     def set_stream(self, stream):

@@ -435,6 +435,35 @@ def test_P10_deposited_partition_equals_replicated():
         assert np.abs(Bb1[s] - Bb2[s]).max() <= 1e-13
 
 
+def test_P10_deposited_multistep_sums_once():
+    """A run with J held fixed sums deposited partial currents once: n steps
+    from a random partition equal n steps from the replicated owner values,
+    and the returned J equals the replicated J."""
+    N = (12, 8, 10)
+    lo, n, g = synth.uniform_decomposition(N, (2, 2, 1), 2)
+    dec = O.Decomposition(N, lo, n, g)
+    d, p, c, dt = (1.0, 1.0, 1.0), 8, 1.0, 0.4
+    E, B, J = random_state((N[2], N[1], N[0]), 75, p=p)
+    Jrep = O.scatter(J, dec)
+    r = synth.rng(10, synth.STREAM_PART)
+    cnt = np.zeros((N[2], N[1], N[0]))
+    for s in range(dec.nsub):
+        ix, iy, iz = dec.global_index(s)
+        Z, Y, X = np.meshgrid(iz, iy, ix, indexing="ij")
+        np.add.at(cnt, (Z, Y, X), 1.0)
+    Jdep = []
+    for s in range(dec.nsub):  # equal split among the copies
+        ix, iy, iz = dec.global_index(s)
+        Z, Y, X = np.meshgrid(iz, iy, ix, indexing="ij")
+        Jdep.append(J[:, Z, Y, X] / cnt[Z, Y, X])
+    e1, b1, j1 = O.run_local(O.scatter(E, dec), O.scatter(B, dec), Jdep, dec, d, p, c, dt, 3,
+                             "deposited")
+    e2, b2, j2 = O.run_local(O.scatter(E, dec), O.scatter(B, dec), Jrep, dec, d, p, c, dt, 3)
+    for s in range(dec.nsub):
+        assert np.abs(e1[s] - e2[s]).max() <= 1e-13 and np.abs(b1[s] - b2[s]).max() <= 1e-13
+        assert np.abs(j1[s] - Jrep[s]).max() <= 1e-14
+
+
 def test_P10_consistency_after_step():
     dec = tiny_uneven()
     d, p, c, dt = (1.0, 1.0, 1.0), 4, 1.0, 0.3
