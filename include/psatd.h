@@ -161,16 +161,19 @@ psatd_status psatd_step(psatd_plan_t plan, void* const E[3], void* const B[3], v
 
 /*
  * psatd_run -- nsteps >= 0 steps with J unchanged, replayed from a captured HIP graph
- * (captured once per (buffers, nsteps) and cached in the plan).  In PSATD_J_DEPOSITED
- * mode the partial currents are summed once, at the first step, and then held.
+ * (captured once per (buffers, nsteps) and cached in the plan).  J is exchanged once, at
+ * the first step (summed in PSATD_J_DEPOSITED mode, filled from the owners in
+ * PSATD_J_REPLICATED mode), and then held: the step never writes J, so the later steps
+ * find it consistent.
  */
 psatd_status psatd_run(psatd_plan_t plan, void* const E[3], void* const B[3], void* const J[3],
                        int32_t nsteps);
 
 /*
- * psatd_run_profiled -- nsteps >= 1 steps launched directly with a HIP event pair
- * around every phase; waits for completion and writes the mean milliseconds per step
- * of each phase to phase_ms[PSATD_NPHASES] (host array).
+ * psatd_run_profiled -- nsteps >= 1 steps (psatd_step semantics, J exchanged every step)
+ * launched directly with a HIP event pair around every kernel launch; waits for
+ * completion and writes the mean milliseconds per step of each phase to
+ * phase_ms[PSATD_NPHASES] (host array).
  */
 psatd_status psatd_run_profiled(psatd_plan_t plan, void* const E[3], void* const B[3],
                                 void* const J[3], int32_t nsteps, double* phase_ms);

@@ -103,8 +103,11 @@ psatd_status check_fields(psatd_plan_t p, void* const* v, int count, const char*
 
 // One step: exchange_J, every batch through F -> U -> I, exchange_EB.  If prof
 // is given, an event pair brackets every launch, tagged with its phase.
+// first: the first step since J was (re)deposited or changed.  J is read-only
+// in the step, so its guard exchange (sum and/or fill) is needed only then;
+// later steps of a run with J held fixed find it already consistent.
 psatd_status enqueue_step(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3],
-                          hipStream_t st, bool deposit,
+                          hipStream_t st, bool first,
                           std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>* prof = nullptr) {
   const DevPlan& d = p->dp;
   void* eb[6] = {E[0], E[1], E[2], B[0], B[1], B[2]};
@@ -125,10 +128,12 @@ psatd_status enqueue_step(psatd_plan_t p, void* const E[3], void* const B[3], vo
   psatd_status r;
 #define PSATD_MARK(ph, s0) \
   if ((r = mark(ph, s0)) != PSATD_OK) return r
-  PSATD_MARK(kPhaseExchJ, true);
-  if (deposit) HIPCHK(p, launch_sum(d, J, st));
-  HIPCHK(p, launch_fill(d, J, 3, st));
-  PSATD_MARK(kPhaseExchJ, false);
+  if (first) {
+    PSATD_MARK(kPhaseExchJ, true);
+    if (p->h.jmode == PSATD_J_DEPOSITED) HIPCHK(p, launch_sum(d, J, st));
+    HIPCHK(p, launch_fill(d, J, 3, st));
+    PSATD_MARK(kPhaseExchJ, false);
+  }
   for (const Batch& b : p->h.batches) {
     PSATD_MARK(kPhaseFwd, true);
     HIPCHK(p, launch_fwd(d, b, in9, p->ws, st));
@@ -365,7 +370,7 @@ psatd_status psatd_set_workspace(psatd_plan_t p, void* dev, int64_t bytes) {
 psatd_status psatd_step(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3]) {
   psatd_status r = check_step_args(p, E, B, J);
   if (r != PSATD_OK) return r;
-  return enqueue_step(p, E, B, J, p->stream, p->h.jmode == PSATD_J_DEPOSITED);
+  return enqueue_step(p, E, B, J, p->stream, true);
 }
 
 psatd_status psatd_run(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3],
@@ -386,7 +391,7 @@ psatd_status psatd_run(psatd_plan_t p, void* const E[3], void* const B[3], void*
     HIPCHK(p, hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed));
     psatd_status er = PSATD_OK;
     for (int i = 0; i < nsteps && er == PSATD_OK; ++i)
-      er = enqueue_step(p, E, B, J, p->cap_stream, i == 0 && p->h.jmode == PSATD_J_DEPOSITED);
+      er = enqueue_step(p, E, B, J, p->cap_stream, i == 0);
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
     if (er != PSATD_OK) {
@@ -426,7 +431,7 @@ psatd_status psatd_run_profiled(psatd_plan_t p, void* const E[3], void* const B[
   }
   double acc[kNumPhases] = {0, 0, 0, 0, 0};
   for (int stp = 0; stp < nsteps && out == PSATD_OK; ++stp) {
-    out = enqueue_step(p, E, B, J, p->stream, stp == 0 && p->h.jmode == PSATD_J_DEPOSITED, &ev);
+    out = enqueue_step(p, E, B, J, p->stream, true, &ev);
     if (out != PSATD_OK) break;
     if (hipEventSynchronize(ev[npairs - 1].second.second) != hipSuccess) { out = fail(p, PSATD_E_HIP, "hipEventSynchronize"); break; }
     for (size_t i = 0; i < npairs; ++i) {

@@ -170,14 +170,19 @@ struct UpdConst {
 //   B' = C B - i (S/ck) [k]xE + i (X1/c^2) [k]xJ
 // C = cos th, S = sin th, th = c|[k]|dt, X1 = (1-C)/|[k]|^2 = 2 sin^2(th/2)/|[k]|^2,
 // X2 = (S/ck - dt)/|[k]|^2 (series below th = 0.1); k -> 0 limits at |[k]| = 0.
-template <typename T>
+//
+// INC: return the increments E' - E and B' - B instead (C replaced by
+// C - 1 = -2 sin^2(th/2), exact without cancellation).  The FP32 path moves the
+// increment through the FFTs: for resolved fields it is far smaller than E,
+// so the FFT roundoff, relative to what is transformed, shrinks with it.
+template <typename T, bool INC = false>
 PSATD_HD void psatd_point(T* vr, T* vi /* E0 E1 E2 B0 B1 B2 J0 J1 J2 */, double kx, double ky,
                           double kz, double c, double dt) {
   const double k2 = kx * kx + ky * ky + kz * kz;
   double C, Sck, X1, X2;
   const double c2 = c * c;
   if (k2 == 0.0) {
-    C = 1.0;
+    C = INC ? 0.0 : 1.0;
     Sck = dt;
     X1 = 0.5 * c2 * dt * dt;
     X2 = -c2 * dt * dt * dt / 6.0;
@@ -185,7 +190,7 @@ PSATD_HD void psatd_point(T* vr, T* vi /* E0 E1 E2 B0 B1 B2 J0 J1 J2 */, double 
     const double k = sqrt(k2);
     const double th = c * k * dt;
     const double sh = sin(0.5 * th), ch = cos(0.5 * th);
-    C = 1.0 - 2.0 * sh * sh;
+    C = INC ? -2.0 * sh * sh : 1.0 - 2.0 * sh * sh;
     Sck = (2.0 * sh * ch) / (c * k);
     X1 = 2.0 * sh * sh / k2;
     const double t2 = th * th;
@@ -243,7 +248,7 @@ struct UpdArgs {
 // [z][f * PB + p] (W = 9 PB complex per z row), so that all 9 (then the 6
 // output) fields are transformed by one multi-transform pass with a uniform
 // element stride W.  Pencils past the end of the box (last block) are zeros.
-template <typename T, int PB, class Bar>
+template <typename T, int PB, bool INC, class Bar>
 PSATD_HD void body_z_update(const UpdArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar) {
   const int s = find_box(a.items, a.t.nsub, item);
   const BoxD& bx = a.t.box[s];
@@ -303,7 +308,7 @@ PSATD_HD void body_z_update(const UpdArgs<T>& a, int item, int tid, int nt, cx<T
     const int q = q0 + p;
     const int ky = (int)fdiv((uint32_t)q, dH);
     const int kx = q - ky * H;
-    psatd_point(vr, vi, kxt[kx], kyt[ky], kzt[plan_index(plz, slot)], a.k.c, a.k.dt);
+    psatd_point<T, INC>(vr, vi, kxt[kx], kyt[ky], kzt[plan_index(plz, slot)], a.k.c, a.k.dt);
 #pragma unroll
     for (int f = 0; f < 6; ++f) row[f * PB] = cx<T>{vr[f], vi[f]};
   }
@@ -345,7 +350,7 @@ struct InvArgs {
 
 // LDS: the plane with row stride ld, then the twiddles of the y plan (Py),
 // the x plan (Nh) and W_Px.
-template <typename T, class Bar>
+template <typename T, bool INC, class Bar>
 PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar) {
   const int s = find_box(a.items, a.t.nsub, item);
   const BoxD& bx = a.t.box[s];
@@ -408,7 +413,8 @@ PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>*
                      },
                      [&](int i, T v) {
                        const int yy = (int)fdiv((uint32_t)i, dnx);
-                       dst[(gy + yy) * Px + gx + (i - yy * nx)] = v;
+                       T* q = dst + (gy + yy) * Px + gx + (i - yy * nx);
+                       *q = INC ? *q + v : v;  // INC: v is the increment
                      });
 }
 

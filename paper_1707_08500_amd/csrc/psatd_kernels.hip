@@ -38,20 +38,20 @@ __global__ __launch_bounds__(kThreadsXY) void k_fwd_xy(FwdArgs<T> a, int item0, 
   }
 }
 
-template <typename T>
+template <typename T, bool INC>
 __global__ __launch_bounds__(kThreadsXY) void k_inv_xy(InvArgs<T> a, int item0, int nitems, int remap) {
   cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
   for (int it = first_item(remap); it < nitems; it += gridDim.x) {
-    body_inv_xy(a, item0 + it, threadIdx.x, blockDim.x, lds, BlockBarrier{});
+    body_inv_xy<T, INC>(a, item0 + it, threadIdx.x, blockDim.x, lds, BlockBarrier{});
     __syncthreads();
   }
 }
 
-template <typename T, int NT, int PB>
+template <typename T, int NT, int PB, bool INC>
 __global__ __launch_bounds__(NT) void k_z_update(UpdArgs<T> a, int item0, int nitems, int remap) {
   cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
   for (int it = first_item(remap); it < nitems; it += gridDim.x) {
-    body_z_update<T, PB>(a, item0 + it, threadIdx.x, NT, lds, BlockBarrier{});
+    body_z_update<T, PB, INC>(a, item0 + it, threadIdx.x, NT, lds, BlockBarrier{});
     __syncthreads();
   }
 }
@@ -106,13 +106,17 @@ static Tables<T> tables(const DevPlan& p) {
   return t;
 }
 
+// The FP32 path transforms increments (INC), the FP64 path the new fields.
+template <typename T> struct IncOf { static constexpr bool value = sizeof(T) == 4; };
+
 template <typename T>
 static hipError_t set_upd_attr(int lds) {
+  constexpr bool I = IncOf<T>::value;
   const void* fns[] = {
-      (const void*)k_z_update<T, 512, 2>,  (const void*)k_z_update<T, 512, 4>,
-      (const void*)k_z_update<T, 512, 8>,  (const void*)k_z_update<T, 512, 16>,
-      (const void*)k_z_update<T, 1024, 2>, (const void*)k_z_update<T, 1024, 4>,
-      (const void*)k_z_update<T, 1024, 8>, (const void*)k_z_update<T, 1024, 16>};
+      (const void*)k_z_update<T, 512, 2, I>,  (const void*)k_z_update<T, 512, 4, I>,
+      (const void*)k_z_update<T, 512, 8, I>,  (const void*)k_z_update<T, 512, 16, I>,
+      (const void*)k_z_update<T, 1024, 2, I>, (const void*)k_z_update<T, 1024, 4, I>,
+      (const void*)k_z_update<T, 1024, 8, I>, (const void*)k_z_update<T, 1024, 16, I>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
@@ -124,11 +128,11 @@ hipError_t prepare_kernels(bool f64, int ldsF, int ldsI, int ldsU) {
   hipError_t e;
   if (f64) {
     if ((e = hipFuncSetAttribute((const void*)k_fwd_xy<double>, hipFuncAttributeMaxDynamicSharedMemorySize, ldsF)) != hipSuccess) return e;
-    if ((e = hipFuncSetAttribute((const void*)k_inv_xy<double>, hipFuncAttributeMaxDynamicSharedMemorySize, ldsI)) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute((const void*)k_inv_xy<double, IncOf<double>::value>, hipFuncAttributeMaxDynamicSharedMemorySize, ldsI)) != hipSuccess) return e;
     return set_upd_attr<double>(ldsU);
   }
   if ((e = hipFuncSetAttribute((const void*)k_fwd_xy<float>, hipFuncAttributeMaxDynamicSharedMemorySize, ldsF)) != hipSuccess) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_inv_xy<float>, hipFuncAttributeMaxDynamicSharedMemorySize, ldsI)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_inv_xy<float, IncOf<float>::value>, hipFuncAttributeMaxDynamicSharedMemorySize, ldsI)) != hipSuccess) return e;
   return set_upd_attr<float>(ldsU);
 }
 
@@ -194,7 +198,7 @@ hipError_t launch_fwd(const DevPlan& p, const Batch& b, void* const* in9, void* 
 
 template <typename T, int NT, int PB>
 static hipError_t upd_launch(const DevPlan& p, const Batch& b, const UpdArgs<T>& a, int g, hipStream_t st) {
-  hipLaunchKernelGGL((k_z_update<T, NT, PB>), dim3(g), dim3(NT), p.ldsU, st, a, b.U0, b.nU, p.xcd);
+  hipLaunchKernelGGL((k_z_update<T, NT, PB, IncOf<T>::value>), dim3(g), dim3(NT), p.ldsU, st, a, b.U0, b.nU, p.xcd);
   return hipGetLastError();
 }
 
@@ -235,7 +239,7 @@ static hipError_t inv_t(const DevPlan& p, const Batch& b, const void* spec, void
   for (int f = 0; f < 6; ++f) a.out[f] = reinterpret_cast<T*>(out6[f]);
   const int g = grid_for(b.nI, p.grid_cap[kPhaseInv]);
   if (!g) return hipSuccess;
-  hipLaunchKernelGGL(k_inv_xy<T>, dim3(g), dim3(kThreadsXY), p.ldsI, st, a, b.I0, b.nI, p.xcd);
+  hipLaunchKernelGGL((k_inv_xy<T, IncOf<T>::value>), dim3(g), dim3(kThreadsXY), p.ldsI, st, a, b.I0, b.nI, p.xcd);
   return hipGetLastError();
 }
 

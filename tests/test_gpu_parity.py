@@ -312,3 +312,80 @@ def test_fp32_error_after_100_steps_vs_fp64_gpu():
                        (np.sum(bE ** 2) + np.sum(bB ** 2))))
     say(f"  per component (Ex..Bz) {['%.2e' % v for v in per]}  energy-norm {en:.3e}")
     assert en <= TOL32
+
+
+# ------------------------- configuration 4: uneven boxes at full size, sampled
+def config4_fields(N, d, case=4):
+    """Gaussian current pulse plus 8 background plane waves (|m_u| <= 8,
+    amplitude 0.1, polarisation orthogonal to [k] of order 64)."""
+    J = synth.current_pulses(N, d, case=case, count=1, sigma=8.0)
+    ms, amps, phases = synth.wave_parameters(case=case, count=8, mmax=8)
+    E = np.zeros((3, N[2], N[1], N[0]))
+    B = np.zeros_like(E)
+    for m, a, ph in zip(ms, amps, phases):
+        kv = np.array([O.modified_k(N[u], d[u], 64)[m[u] % N[u]] for u in range(3)])
+        a = O.project_transverse(a, kv)
+        a = 0.1 * a / np.linalg.norm(a)
+        kh = kv / np.linalg.norm(kv)
+        E += synth.plane_wave(N, m, a, ph)
+        B += synth.plane_wave(N, m, np.cross(kh, a), ph)
+    return E, B, J
+
+
+def test_config4_uneven_full_size_one_step_sampled():
+    """512x512x256 cut into uneven boxes (edges from {48,64,80,96}, guards from
+    {8,16,32}), p = 64, FP32, all boxes in one launch per phase: one step on the
+    GPU, four boxes of different shapes recomputed by the oracle."""
+    say("config 4 full size, uneven, sampled boxes")
+    N = (512, 512, 256)
+    d = (1.0, 1.0, 1.0)
+    p, dt, c = 64, 0.5, 1.0
+    lo, n, g = synth.uneven_decomposition(N, case=4)
+    E, B, J = config4_fields(N, d)
+    case = GpuCase(N, lo, n, g, p, dt, c, "f32", "replicated", E, B, J)
+    case.plan.run(case.E, case.B, case.J, 1)
+    case.plan.sync()
+    dec = case.dec
+    shapes = {}
+    for s in range(dec.nsub):
+        shapes.setdefault(tuple(dec.padded(s)), s)
+    sample = sorted(shapes.values(), key=lambda s: -int(np.prod(dec.padded(s))))[:2] + [0, dec.nsub - 1]
+    gE = case.boxes(case.E, sample)
+    gB = case.boxes(case.B, sample)
+
+    def box(F, s):
+        ix, iy, iz = dec.global_index(s)
+        return F[:, iz[:, None, None], iy[None, :, None], ix[None, None, :]]
+    num = den = 0.0
+    for s in sample:
+        e1, b1 = O.step_global(box(E, s).astype(np.float32).astype(np.float64),
+                               box(B, s).astype(np.float32).astype(np.float64),
+                               box(J, s).astype(np.float32).astype(np.float64), d, p, c, dt)
+        gx, gy, gz = dec.g[s]
+        nx, ny, nz = dec.n[s]
+        sl = (slice(None), slice(gz, gz + nz), slice(gy, gy + ny), slice(gx, gx + nx))
+        dn = float(np.sum((gE[s][sl] - e1[sl]) ** 2) + c * c * np.sum((gB[s][sl] - b1[sl]) ** 2))
+        dd = float(np.sum(e1[sl] ** 2) + c * c * np.sum(b1[sl] ** 2))
+        say(f"  box {s} padded {dec.padded(s)}: energy-norm rel-L2 {np.sqrt(dn / dd):.3e}")
+        num += dn
+        den += dd
+    en = float(np.sqrt(num / den))
+    assert en <= TOL32
+
+
+# ----------------- configuration 5 cutout: 176^3 local boxes, p = 100
+@pytest.mark.parametrize("precision,tol", [("f32", TOL32)])
+def test_config5_cutout(precision, tol):
+    """Same local shape and order as configuration 5 (128^3 + 24 guards =
+    176^3, p = 100) on a 256^3 grid of 2x2x2 boxes, laser-like pulse plus
+    Gaussian currents, one step, every box compared with the oracle."""
+    say(f"config 5 cutout {precision}")
+    N = (256, 256, 256)
+    d = (1.0, 1.0, 1.0)
+    lo, n, g = synth.uniform_decomposition(N, (2, 2, 2), 24)
+    E, B = synth.laser_pulse(N, d, c=1.0, wavelength=32.0, x_c=128.0, width=32.0)
+    J = synth.current_pulses(N, d, case=5, count=4, sigma=8.0, amp_range=(0.0, 0.1))
+    if precision == "f32":
+        E, B, J = (x.astype(np.float32).astype(np.float64) for x in (E, B, J))
+    case, eE, eB, _ = run_both(N, lo, n, g, 100, 0.5, 1.0, precision, "replicated", (E, B, J), 1)
+    check(case, eE, eB, precision, tol)
