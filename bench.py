@@ -127,6 +127,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=5)
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -164,12 +165,17 @@ def main():
         glob = [[torch.from_numpy(np.ascontiguousarray(F[a])).to("cuda", dtype).reshape(-1)
                  for a in range(3)] for F in (E0, B0, J0)]
         E, B, J = plan.empty_fields(), plan.empty_fields(), plan.empty_fields()
+        if not args.no_autotune:
+            for F, pad in zip(glob, (E, B, J)):
+                plan.scatter(F, pad)
+            tuned_ms = plan.autotune(E, B, J, steps_per_trial=3)
+            log(f"[bench] {prec}: autotuned {plan.tuning()} ({tuned_ms:.3f} ms/step in trials)")
         log(f"[bench] {prec}: {args.warmup} warmup + {args.steps} timed steps")
         t = timed_run(plan, E, B, J, glob, args.steps, args.warmup)
         padded = plan.field_elems
         results[prec] = dict(seconds=t, ms_per_step=1e3 * t / args.steps,
                              value=interior * args.steps / t,
-                             padded_value=padded * args.steps / t)
+                             padded_value=padded * args.steps / t, tuning=plan.tuning())
         outE = [torch.empty_like(x) for x in glob[0]]
         outB = [torch.empty_like(x) for x in glob[1]]
         plan.gather(E, outE)
@@ -209,8 +215,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl["desc"] + "; FP32 state, FP32 VALU radix FFT, FP64 coefficients and update",
-                   "global_batch": interior, "precision": "f32_valu", "graph": True},
+        "config": {"workload": wl["desc"] + "; FP32 state, FP32 VALU radix FFT of increments, FP64 coefficients",
+                   "global_batch": interior, "precision": "f32_valu", "graph": True,
+                   "tuning": r32["tuning"]},
         "padded_cell_updates_per_s": r32["padded_value"],
         "phases_ms": phases,
         "hbm_fraction_of_step": {

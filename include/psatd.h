@@ -84,7 +84,7 @@ enum {
 
 /* Launch-shape knobs (psatd_set_tuning).  None changes results beyond rounding order. */
 typedef enum {
-  PSATD_TUNE_Z_PENCILS = 0,  /* (ky,kx) pencils per z-update work-group: 2, 4, 8 or 16 (LDS-limited) */
+  PSATD_TUNE_Z_PENCILS = 0,  /* (ky,kx) pencils per z-update work-group: 4, 8 or 16 (LDS-limited) */
   PSATD_TUNE_XCD_REMAP = 1,  /* 1: consecutive work items on the same XCD (shared L2); 0: dispatch order */
   PSATD_TUNE_GRID_FWD = 2,   /* work-groups of the forward x/y pass: 0 = one per item, else a persistent grid */
   PSATD_TUNE_GRID_UPD = 3,   /* same for the z-update pass */
@@ -92,7 +92,13 @@ typedef enum {
   PSATD_TUNE_GRID_EXCH = 5,  /* same for the guard exchanges */
   PSATD_TUNE_BATCH_BOXES = 6, /* subdomains pushed through the FFT/update passes together (0 = all);
                                  the workspace then holds one batch's half spectra */
-  PSATD_NTUNE = 7
+  PSATD_TUNE_MAX_RADIX = 7,   /* largest radix of the FFT schedules: 16, or 8 (fewer registers, more
+                                 stages); radix 11 is always allowed */
+  PSATD_TUNE_XY_THREADS = 8,  /* threads per work-group of the x/y passes: 256 or 512 */
+  PSATD_TUNE_Z_THREADS = 9,   /* threads per work-group of the z-update: 512 or 1024 */
+  PSATD_TUNE_SPLIT_XY = 10,   /* 1: x rows and y columns in separate passes through the workspace
+                                 (automatic when a padded plane exceeds the LDS; needs no batching) */
+  PSATD_NTUNE = 11
 } psatd_tune_key;
 
 /*
@@ -112,9 +118,8 @@ typedef enum {
  *   precision   psatd_precision
  *   jmode       psatd_jmode
  *   stream      hipStream_t on which all work is enqueued (NULL = default stream)
- * Padded lengths must have prime factors <= 11, the padded x length must be even, and
- * one padded (y, x/2+1) complex plane must fit the 160 KiB LDS of a compute unit at the
- * plan's precision; otherwise PSATD_E_UNSUPPORTED.  Uses the current HIP device.
+ * Padded lengths must have prime factors <= 11 and the padded x length must be even;
+ * otherwise PSATD_E_UNSUPPORTED.  Uses the current HIP device.
  * On success *out receives the plan; on failure *out is NULL.
  */
 psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double grid_d[3],
@@ -200,6 +205,18 @@ psatd_status psatd_modified_k(psatd_plan_t plan, int32_t s, int32_t axis, double
  */
 psatd_status psatd_set_tuning(psatd_plan_t plan, int32_t key, int32_t value);
 psatd_status psatd_get_tuning(psatd_plan_t plan, int32_t key, int32_t* value);
+
+/*
+ * psatd_autotune -- picks the launch shapes (largest radix, x/y threads, z tile and threads,
+ * XCD item order) by timing candidate settings with steps_per_trial >= 1 steps each on the
+ * given buffers, phase by phase, and applies the fastest.  The trial steps advance E and B
+ * (tune before loading the state that matters).  cache_path (may be NULL): a text file of
+ * "key value..." lines; a hit applies the cached setting without timing, a miss appends the
+ * new result.  The key holds the device name, the precision and the padded box shapes.
+ * *best_ms (may be NULL) receives the tuned step time in milliseconds (0 on a cache hit).
+ */
+psatd_status psatd_autotune(psatd_plan_t plan, void* const E[3], void* const B[3], void* const J[3],
+                            int32_t steps_per_trial, const char* cache_path, double* best_ms);
 
 psatd_status psatd_set_stream(psatd_plan_t plan, void* stream);
 psatd_status psatd_sync(psatd_plan_t plan); /* waits for the plan's stream */

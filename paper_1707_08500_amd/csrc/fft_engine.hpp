@@ -216,13 +216,18 @@ PSATD_HD void fft_stage(cx<T>* buf, int M, FastDiv dM, int ms, int es, int N, in
   const int nb = N / R;
   const int twstep = N / L;
   const int total = M * nb;
+  if (tid >= total) return;
+  // butterfly b = w M + m, advanced incrementally by nt per iteration
+  int w = (int)fdiv((uint32_t)tid, dM);
+  int m = tid - w * M;
+  const int dw = (int)fdiv((uint32_t)nt, dM);
+  const int dm = nt - dw * M;
+  const int step = mstride * es;
   for (int b = tid; b < total; b += nt) {
-    const int w = (int)fdiv((uint32_t)b, dM);
-    const int m = b - w * M;
     const int blk = (int)fdiv((uint32_t)w, dS);
     const int j = w - blk * mstride;
     cx<T>* p = buf + m * ms + (blk * L + j) * es;
-    const int step = mstride * es;
+    const int jt = j * twstep;
     cx<T> a[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) a[q] = p[q * step];
@@ -230,21 +235,29 @@ PSATD_HD void fft_stage(cx<T>* buf, int M, FastDiv dM, int ms, int es, int N, in
       Dft<R, DIR, T>::run(a);
       if (j) {
 #pragma unroll
-        for (int t = 1; t < R; ++t) a[t] = cmul(a[t], twid<DIR>(tw, j * t * twstep));
+        for (int t = 1; t < R; ++t) a[t] = cmul(a[t], twid<DIR>(tw, jt * t));
       }
     } else {
       if (j) {
 #pragma unroll
-        for (int t = 1; t < R; ++t) a[t] = cmul(a[t], twid<DIR>(tw, j * t * twstep));
+        for (int t = 1; t < R; ++t) a[t] = cmul(a[t], twid<DIR>(tw, jt * t));
       }
       Dft<R, DIR, T>::run(a);
     }
 #pragma unroll
     for (int q = 0; q < R; ++q) p[q * step] = a[q];
+    m += dm;
+    w += dw;
+    if (m >= M) {
+      m -= M;
+      ++w;
+    }
   }
 }
 
-template <int DIR, bool DIF, typename T>
+// MAXR bounds the codelets compiled into a kernel (registers scale with the
+// largest one); radices 2..8 and 11 are always present.
+template <int DIR, bool DIF, int MAXR, typename T>
 PSATD_HD void fft_stage_dispatch(int R, cx<T>* buf, int M, FastDiv dM, int ms, int es, int N, int L,
                                  FastDiv dS, const cx<T>* tw, int tid, int nt) {
   switch (R) {
@@ -255,17 +268,17 @@ PSATD_HD void fft_stage_dispatch(int R, cx<T>* buf, int M, FastDiv dM, int ms, i
     case 6: fft_stage<6, DIR, DIF>(buf, M, dM, ms, es, N, L, dS, tw, tid, nt); break;
     case 7: fft_stage<7, DIR, DIF>(buf, M, dM, ms, es, N, L, dS, tw, tid, nt); break;
     case 8: fft_stage<8, DIR, DIF>(buf, M, dM, ms, es, N, L, dS, tw, tid, nt); break;
-    case 10: fft_stage<10, DIR, DIF>(buf, M, dM, ms, es, N, L, dS, tw, tid, nt); break;
+    case 10: if (MAXR >= 10) fft_stage<10, DIR, DIF>(buf, M, dM, ms, es, N, L, dS, tw, tid, nt); break;
     case 11: fft_stage<11, DIR, DIF>(buf, M, dM, ms, es, N, L, dS, tw, tid, nt); break;
-    case 12: fft_stage<12, DIR, DIF>(buf, M, dM, ms, es, N, L, dS, tw, tid, nt); break;
-    case 16: fft_stage<16, DIR, DIF>(buf, M, dM, ms, es, N, L, dS, tw, tid, nt); break;
+    case 12: if (MAXR >= 12) fft_stage<12, DIR, DIF>(buf, M, dM, ms, es, N, L, dS, tw, tid, nt); break;
+    case 16: if (MAXR >= 16) fft_stage<16, DIR, DIF>(buf, M, dM, ms, es, N, L, dS, tw, tid, nt); break;
     default: break;  // plans only hold the radices above (checked at plan time)
   }
 }
 
 // natural -> stage-digit order; ends with a barrier.  tw: this plan's W_N^e
 // table (global or LDS).  The plan is read from uniform memory.
-template <int DIR, typename T, class Bar>
+template <int DIR, int MAXR, typename T, class Bar>
 PSATD_HD void fft_dif(cx<T>* buf, int M, int ms, int es, const FftPlanD* pl, const cx<T>* tw,
                       int tid, int nt, Bar bar) {
   const int N = pl->N;
@@ -274,14 +287,14 @@ PSATD_HD void fft_dif(cx<T>* buf, int M, int ms, int es, const FftPlanD* pl, con
   int L = N;
   for (int s = 0; s < ns; ++s) {
     const int R = pl->radix[s];
-    fft_stage_dispatch<DIR, true, T>(R, buf, M, dM, ms, es, N, L, pl->sdiv[s], tw, tid, nt);
+    fft_stage_dispatch<DIR, true, MAXR, T>(R, buf, M, dM, ms, es, N, L, pl->sdiv[s], tw, tid, nt);
     bar();
     L /= R;
   }
 }
 
 // stage-digit -> natural order; ends with a barrier
-template <int DIR, typename T, class Bar>
+template <int DIR, int MAXR, typename T, class Bar>
 PSATD_HD void fft_dit(cx<T>* buf, int M, int ms, int es, const FftPlanD* pl, const cx<T>* tw,
                       int tid, int nt, Bar bar) {
   const int N = pl->N;
@@ -289,7 +302,7 @@ PSATD_HD void fft_dit(cx<T>* buf, int M, int ms, int es, const FftPlanD* pl, con
   const FastDiv dM = make_fastdiv((uint32_t)M);
   for (int s = ns - 1; s >= 0; --s) {
     const int L = pl->stride[s] * pl->radix[s];
-    fft_stage_dispatch<DIR, false, T>(pl->radix[s], buf, M, dM, ms, es, N, L, pl->sdiv[s], tw, tid,
+    fft_stage_dispatch<DIR, false, MAXR, T>(pl->radix[s], buf, M, dM, ms, es, N, L, pl->sdiv[s], tw, tid,
                                       nt);
     bar();
   }

@@ -34,55 +34,73 @@ struct HostTables {
   std::vector<int32_t> owner;
   std::vector<int32_t> nbr_off, nbr;
   std::vector<int32_t> itemsF, itemsU, itemsI, itemsP, itemsN;
+  std::vector<int32_t> itemsXF, itemsYF, itemsYI, itemsXI;  // split x/y passes
+  bool split = false;  // x/y pass split into x rows and y columns (large planes)
+  int ldsX = 0, ldsY = 0;
   std::vector<Batch> batches;
   int64_t batch_slab = 0;     // complex elements of one spectral field slab of the largest batch
   int32_t batch_boxes = 0;
   int64_t field_elems = 0;
   int64_t slab = 0;
-  int ldsF = 0, ldsI = 0, ldsU = 0, PB = 0, NTU = 0;
+  int ldsF = 0, ldsI = 0, ldsU = 0, PB = 0;
+  int maxr = 16;      // largest radix used by the FFT schedules (8 or 16; 11 always)
+  int ntxy = 512;     // threads per work-group of the x/y passes
+  int ntu = 512;      // threads per work-group of the z-update (1024 for FP32 by default)
 };
 
 inline bool is_f64(int prec) { return prec == PSATD_F64; }
 inline size_t real_size(int prec) { return is_f64(prec) ? 8 : 4; }
 
-// radix schedule with the fewest stages (radices tried largest first)
-inline bool factorize(int N, std::vector<int>& out) {
-  static const int R[] = {16, 12, 11, 10, 8, 7, 6, 5, 4, 3, 2};
-  if (N == 1) { out.clear(); return true; }
+// Radix schedules: maxr 16 allows every codelet, maxr 8 the radices up to 8 plus 11.
+// Every factorisation of n into exactly `left` radices from R (ordered as in R).
+inline void factor_all(int n, int left, const int* R, int nr, std::vector<int>& acc,
+                       std::vector<std::vector<int>>& out) {
+  if (left == 0) {
+    if (n == 1) out.push_back(acc);
+    return;
+  }
+  for (int i = 0; i < nr; ++i) {
+    if (n % R[i]) continue;
+    acc.push_back(R[i]);
+    factor_all(n / R[i], left - 1, R, nr, acc, out);
+    acc.pop_back();
+  }
+}
+
+// Fewest stages; among those the most balanced (largest smallest radix: fewer
+// index operations per element in the small-radix stage), then the largest
+// first radix.
+inline bool factorize(int N, std::vector<int>& out, int maxr = 16) {
+  static const int R16[] = {16, 12, 11, 10, 8, 7, 6, 5, 4, 3, 2};
+  static const int R8[] = {11, 8, 7, 6, 5, 4, 3, 2};
+  const int* R = maxr >= 16 ? R16 : R8;
+  const int nr = maxr >= 16 ? 11 : 8;
+  out.clear();
+  if (N == 1) return true;
   for (int depth = 1; depth <= kMaxStages; ++depth) {
-    std::vector<int> cur;
-    // depth-first search for a factorisation of exactly `depth` radices
-    struct Rec {
-      static bool go(int n, int left, std::vector<int>& acc) {
-        if (left == 0) return n == 1;
-        for (int r : R) {
-          if (n % r) continue;
-          acc.push_back(r);
-          if (go(n / r, left - 1, acc)) return true;
-          acc.pop_back();
-        }
-        return false;
+    std::vector<std::vector<int>> all;
+    std::vector<int> acc;
+    factor_all(N, depth, R, nr, acc, all);
+    if (all.empty()) continue;
+    const std::vector<int>* best = nullptr;
+    int bmin = -1, bfirst = -1;
+    for (const auto& f : all) {
+      const int mn = *std::min_element(f.begin(), f.end());
+      if (mn > bmin || (mn == bmin && f[0] > bfirst)) {
+        best = &f;
+        bmin = mn;
+        bfirst = f[0];
       }
-    };
-    if (Rec::go(N, depth, cur)) { out = cur; return true; }
+    }
+    out = *best;
+    return true;
   }
   return false;
 }
 
-inline bool small_primes_only(int64_t n) {
-  for (int p : {2, 3, 5, 7, 11})
-    while (n % p == 0) n /= p;
-  return n == 1;
-}
-
-// Adds (or finds) an FFT plan of length N; returns its index or -1.
-inline int add_plan(HostTables& h, int N) {
-  for (size_t i = 0; i < h.plans.size(); ++i)
-    if (h.plans[i].N == N) return (int)i;
-  std::vector<int> rad;
-  if (!factorize(N, rad)) return -1;
-  FftPlanD pl{};
-  pl.N = N;
+// Fills the stage fields of a plan of length pl.N from a radix list.
+inline void set_stages(FftPlanD& pl, const std::vector<int>& rad) {
+  const int N = pl.N;
   pl.nstages = (int)rad.size();
   int prod = 1;
   for (int st = 0; st < kMaxStages; ++st) {
@@ -99,6 +117,23 @@ inline int add_plan(HostTables& h, int N) {
     pl.rdiv[st] = make_fastdiv((uint32_t)pl.radix[st]);
     pl.sdiv[st] = make_fastdiv((uint32_t)pl.stride[st]);
   }
+}
+
+inline bool small_primes_only(int64_t n) {
+  for (int p : {2, 3, 5, 7, 11})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+// Adds (or finds) an FFT plan of length N; returns its index or -1.
+inline int add_plan(HostTables& h, int N) {
+  for (size_t i = 0; i < h.plans.size(); ++i)
+    if (h.plans[i].N == N) return (int)i;
+  std::vector<int> rad;
+  if (!factorize(N, rad, h.maxr)) return -1;
+  FftPlanD pl{};
+  pl.N = N;
+  set_stages(pl, rad);
   pl.tw = (int32_t)h.twr.size();
   const long double PI = 3.141592653589793238462643383279502884L;
   for (int e = 0; e < N; ++e) {
@@ -160,7 +195,8 @@ inline void set_batches(HostTables& h, int per) {
   }
 }
 
-// Work list of the z-update for a tile of PB pencils.
+// Work list of the z-update for a tile of PB pencils (9 fields staged in LDS,
+// plus the z twiddles).
 inline void set_z_tile(HostTables& h, int PB) {
   const int csz = (int)(2 * real_size(h.prec));
   int maxPz = 0;
@@ -171,8 +207,28 @@ inline void set_z_tile(HostTables& h, int PB) {
     maxPz = std::max(maxPz, b.P[2]);
   }
   h.PB = PB;
-  h.ldsU = maxPz * (9 * PB + 1) * csz;  // staged fields + the z twiddles
+  h.ldsU = maxPz * (9 * PB + 1) * csz + maxPz * 4;  // staged fields, z twiddles, z indices
   if (!h.batches.empty()) set_batches(h, h.batch_boxes);
+}
+
+inline bool z_tile_fits(const HostTables& h, int maxPz, int PB) {
+  const int csz = (int)(2 * real_size(h.prec));
+  return (int64_t)maxPz * (9 * PB + 1) * csz + maxPz * 4 <= kMaxDynLds;
+}
+
+// Re-derives every FFT schedule with radices up to maxr (twiddle tables
+// depend on the length only and are kept).  False if a length has no
+// schedule of at most kMaxStages stages.
+inline bool set_max_radix(HostTables& h, int maxr) {
+  std::vector<FftPlanD> plans = h.plans;
+  for (FftPlanD& pl : plans) {
+    std::vector<int> rad;
+    if (!factorize(pl.N, rad, maxr)) return false;
+    set_stages(pl, rad);
+  }
+  h.plans = plans;
+  h.maxr = maxr;
+  return true;
 }
 
 inline int max_padded_z(const HostTables& h) {
@@ -301,8 +357,9 @@ inline psatd_status build_host(HostTables& h, std::string& err, const int64_t gr
     b.soff = soff;
     foff += (int64_t)b.P[0] * b.P[1] * b.P[2];
     soff += (int64_t)b.H * b.P[1] * b.P[2];
-    // plane + twiddles of the x plan, the y plan and W_Px
-    h.ldsF = std::max<int>(h.ldsF, (b.P[1] * b.ld + b.P[0] / 2 + b.P[1] + b.P[0]) * csz);
+    // plane + twiddles of the x plan, the y plan and W_Px + position tables
+    h.ldsF = std::max<int>(h.ldsF, (b.P[1] * b.ld + b.P[0] / 2 + b.P[1] + b.P[0]) * csz +
+                                       (b.P[0] / 2 + b.P[1]) * 4);
     h.ldsI = h.ldsF;
     maxPz = std::max(maxPz, b.P[2]);
   }
@@ -310,17 +367,21 @@ inline psatd_status build_host(HostTables& h, std::string& err, const int64_t gr
     return bad(PSATD_E_UNSUPPORTED, "tables too large");
   h.field_elems = foff;
   h.slab = soff;
-  if (h.ldsF > kMaxDynLds)
-    return bad(PSATD_E_UNSUPPORTED, "a padded (y, x/2+1) plane exceeds the 160 KiB LDS at this precision");
-  // z-update tile: PB consecutive (ky, kx) pencils, all 9 fields staged in LDS
+  // planes that do not fit the LDS take the split x-row / y-column passes
+  h.split = h.ldsF > kMaxDynLds;
+  for (const BoxD& b : h.box) {
+    h.ldsX = std::max<int>(h.ldsX, (kRB * b.ld + b.P[0] / 2 + b.P[0]) * csz + (b.P[0] / 2) * 4);
+    h.ldsY = std::max<int>(h.ldsY, (b.P[1] * kCB + b.P[1]) * csz + b.P[1] * 4);
+  }
+  if (h.ldsX > kMaxDynLds || h.ldsY > kMaxDynLds)
+    return bad(PSATD_E_UNSUPPORTED, "padded lengths too large for the split x/y passes");
+  // z-update tile: PB consecutive (ky, kx) pencils (128-byte rows when possible)
   {
-    int PB = 16;
-    while (PB > 2 && (int64_t)maxPz * (9 * PB + 1) * csz > kMaxDynLds) PB /= 2;
-    if ((int64_t)maxPz * (9 * PB + 1) * csz > kMaxDynLds)
+    int PB = f64 ? 8 : 16;
+    while (PB > 4 && !z_tile_fits(h, maxPz, PB)) PB /= 2;
+    if (!z_tile_fits(h, maxPz, PB))
       return bad(PSATD_E_UNSUPPORTED, "padded z length too large for the z-update kernel");
     h.PB = PB;
-    h.ldsU = maxPz * (9 * PB + 1) * csz;
-    h.NTU = 512;
   }
 
   // neighbours: boxes whose padded region meets the interior of s (for the
@@ -345,12 +406,18 @@ inline psatd_status build_host(HostTables& h, std::string& err, const int64_t gr
     for (int s = 0; s < nsub; ++s) v[s + 1] = v[s] + (int32_t)count(h.box[s]);
   };
   const int PB = h.PB;
+  (void)PB;
   prefix(h.itemsF, [](const BoxD& b) { return (int64_t)b.P[2] * 9; });
   set_z_tile(h, PB);
   prefix(h.itemsI, [](const BoxD& b) { return (int64_t)b.n[2] * 6; });
   prefix(h.itemsP, [](const BoxD& b) { return (int64_t)b.P[2]; });
   prefix(h.itemsN, [](const BoxD& b) { return (int64_t)b.n[2]; });
+  prefix(h.itemsXF, [](const BoxD& b) { return (int64_t)b.P[2] * 9 * ((b.P[1] + kRB - 1) / kRB); });
+  prefix(h.itemsYF, [](const BoxD& b) { return (int64_t)b.P[2] * 9 * ((b.H + kCB - 1) / kCB); });
+  prefix(h.itemsYI, [](const BoxD& b) { return (int64_t)b.n[2] * 6 * ((b.H + kCB - 1) / kCB); });
+  prefix(h.itemsXI, [](const BoxD& b) { return (int64_t)b.n[2] * 6 * ((b.n[1] + kRB - 1) / kRB); });
   set_batches(h, 0);
+  h.ntu = f64 ? 512 : 1024;
   return PSATD_OK;
 }
 

@@ -6,6 +6,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <cstring>
 #include <new>
 #include <string>
@@ -39,7 +42,7 @@ struct psatd_plan_s {
   int device = 0;
   void* blob = nullptr;  // device tables
   int32_t* d_itemsU = nullptr;  // z-update work list (depends on the z tile)
-  int32_t tune[PSATD_NTUNE] = {0, 1, 0, 0, 0, 0, 0};
+  int32_t tune[PSATD_NTUNE] = {0, 1, 0, 0, 0, 0, 0, 16, 256, 512, 0};
   void* ws = nullptr;
   int64_t ws_bytes = 0;
   bool ws_owned = false;
@@ -136,13 +139,23 @@ psatd_status enqueue_step(psatd_plan_t p, void* const E[3], void* const B[3], vo
   }
   for (const Batch& b : p->h.batches) {
     PSATD_MARK(kPhaseFwd, true);
-    HIPCHK(p, launch_fwd(d, b, in9, p->ws, st));
+    if (d.split) {
+      HIPCHK(p, launch_x_fwd(d, in9, p->ws, st));
+      HIPCHK(p, launch_y(d, -1, p->ws, st));
+    } else {
+      HIPCHK(p, launch_fwd(d, b, in9, p->ws, st));
+    }
     PSATD_MARK(kPhaseFwd, false);
     PSATD_MARK(kPhaseUpd, true);
     HIPCHK(p, launch_upd(d, b, p->ws, st));
     PSATD_MARK(kPhaseUpd, false);
     PSATD_MARK(kPhaseInv, true);
-    HIPCHK(p, launch_inv(d, b, p->ws, eb, st));
+    if (d.split) {
+      HIPCHK(p, launch_y(d, 1, p->ws, st));
+      HIPCHK(p, launch_x_inv(d, p->ws, eb, st));
+    } else {
+      HIPCHK(p, launch_inv(d, b, p->ws, eb, st));
+    }
     PSATD_MARK(kPhaseInv, false);
   }
   PSATD_MARK(kPhaseExchEB, true);
@@ -244,6 +257,10 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   const size_t o_iI = reserve(h.itemsI.size() * 4);
   const size_t o_iP = reserve(h.itemsP.size() * 4);
   const size_t o_iN = reserve(h.itemsN.size() * 4);
+  const size_t o_iXF = reserve(h.itemsXF.size() * 4);
+  const size_t o_iYF = reserve(h.itemsYF.size() * 4);
+  const size_t o_iYI = reserve(h.itemsYI.size() * 4);
+  const size_t o_iXI = reserve(h.itemsXI.size() * 4);
   std::vector<unsigned char> hb(total, 0);
   auto put = [&](size_t off, const void* src, size_t bytes) {
     if (bytes) std::memcpy(hb.data() + off, src, bytes);
@@ -268,6 +285,10 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   put(o_iI, h.itemsI.data(), h.itemsI.size() * 4);
   put(o_iP, h.itemsP.data(), h.itemsP.size() * 4);
   put(o_iN, h.itemsN.data(), h.itemsN.size() * 4);
+  put(o_iXF, h.itemsXF.data(), h.itemsXF.size() * 4);
+  put(o_iYF, h.itemsYF.data(), h.itemsYF.size() * 4);
+  put(o_iYI, h.itemsYI.data(), h.itemsYI.size() * 4);
+  put(o_iXI, h.itemsXI.data(), h.itemsXI.size() * 4);
   if ((e = hipMalloc(&p->blob, total)) != hipSuccess) return hipfail(e, "hipMalloc(tables)");
   if ((e = hipMemcpy(p->blob, hb.data(), total, hipMemcpyHostToDevice)) != hipSuccess)
     return hipfail(e, "hipMemcpy(tables)");
@@ -275,13 +296,17 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   if ((e = hipMemcpy(p->d_itemsU, h.itemsU.data(), h.itemsU.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
     return hipfail(e, "hipMemcpy(work list)");
   p->tune[PSATD_TUNE_Z_PENCILS] = h.PB;
+  p->tune[PSATD_TUNE_MAX_RADIX] = h.maxr;
+  p->tune[PSATD_TUNE_XY_THREADS] = h.ntxy;
+  p->tune[PSATD_TUNE_Z_THREADS] = h.ntu;
+  p->tune[PSATD_TUNE_SPLIT_XY] = h.split ? 1 : 0;
   unsigned char* B = reinterpret_cast<unsigned char*>(p->blob);
   // (a1) modified wavenumbers, FP64, on the device
   if ((e = launch_modk(reinterpret_cast<const KEntry*>(B + o_kent), (int)h.kent.size(), h.kmax_len, h.p,
                        reinterpret_cast<double*>(B + o_kmod), p->cap_stream)) != hipSuccess)
     return hipfail(e, "modified-wavenumber kernel");
   if ((e = hipStreamSynchronize(p->cap_stream)) != hipSuccess) return hipfail(e, "modified-wavenumber kernel");
-  if ((e = prepare_kernels(f64, h.ldsF, h.ldsI, h.ldsU)) != hipSuccess)
+  if ((e = prepare_kernels(f64, h.ldsF, h.ldsI, h.ldsU, h.ldsX, h.ldsY)) != hipSuccess)
     return hipfail(e, "hipFuncSetAttribute");
 
   DevPlan& d = p->dp;
@@ -306,6 +331,17 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   d.itemsI = reinterpret_cast<const int32_t*>(B + o_iI);
   d.itemsP = reinterpret_cast<const int32_t*>(B + o_iP);
   d.itemsN = reinterpret_cast<const int32_t*>(B + o_iN);
+  d.itemsXF = reinterpret_cast<const int32_t*>(B + o_iXF);
+  d.itemsYF = reinterpret_cast<const int32_t*>(B + o_iYF);
+  d.itemsYI = reinterpret_cast<const int32_t*>(B + o_iYI);
+  d.itemsXI = reinterpret_cast<const int32_t*>(B + o_iXI);
+  d.nXF = h.itemsXF.back();
+  d.nYF = h.itemsYF.back();
+  d.nYI = h.itemsYI.back();
+  d.nXI = h.itemsXI.back();
+  d.ldsX = h.ldsX;
+  d.ldsY = h.ldsY;
+  d.split = h.split ? 1 : 0;
   d.nF = h.itemsF.back();
   d.nU = h.itemsU.back();
   d.nI = h.itemsI.back();
@@ -315,7 +351,9 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   d.ldsI = h.ldsI;
   d.ldsU = h.ldsU;
   d.PB = h.PB;
-  d.NTU = h.NTU;
+  d.ntu = h.ntu;
+  d.ntxy = h.ntxy;
+  d.maxr = h.maxr;
   d.xcd = 1;
   d.slab = h.batch_slab;
   d.c = h.c;
@@ -487,22 +525,30 @@ psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
   DevPlan& d = p->dp;
   switch (key) {
     case PSATD_TUNE_Z_PENCILS: {
-      if (value != 2 && value != 4 && value != 8 && value != 16)
-        return fail(p, PSATD_E_INVALID, "z pencils must be 2, 4, 8 or 16");
-      const int csz = (int)(2 * real_size(p->h.prec));
-      if ((int64_t)max_padded_z(p->h) * (9 * value + 1) * csz > kMaxDynLds)
+      if (value != 4 && value != 8 && value != 16) return fail(p, PSATD_E_INVALID, "z pencils must be 4, 8 or 16");
+      if (!z_tile_fits(p->h, max_padded_z(p->h), value))
         return fail(p, PSATD_E_INVALID, "z tile does not fit the LDS");
       HIPCHK(p, hipStreamSynchronize(p->stream));
       set_z_tile(p->h, value);
       HIPCHK(p, hipMemcpy(p->d_itemsU, p->h.itemsU.data(), p->h.itemsU.size() * 4, hipMemcpyHostToDevice));
-      HIPCHK(p, prepare_kernels(d.f64, p->h.ldsF, p->h.ldsI, p->h.ldsU));
+      HIPCHK(p, prepare_kernels(d.f64, p->h.ldsF, p->h.ldsI, p->h.ldsU, p->h.ldsX, p->h.ldsY));
       d.PB = p->h.PB;
       d.ldsU = p->h.ldsU;
       d.nU = p->h.itemsU.back();
       break;
     }
+    case PSATD_TUNE_SPLIT_XY: {
+      if (value != 0 && value != 1) return fail(p, PSATD_E_INVALID, "split must be 0 or 1");
+      if (!value && p->h.ldsF > kMaxDynLds) return fail(p, PSATD_E_INVALID, "the padded planes need the split passes");
+      if (value && p->h.batches.size() > 1) return fail(p, PSATD_E_INVALID, "the split passes do not batch");
+      p->h.split = value != 0;
+      d.split = value;
+      break;
+    }
     case PSATD_TUNE_BATCH_BOXES: {
       if (value < 0) return fail(p, PSATD_E_INVALID, "boxes per batch must be >= 0");
+      if (value > 0 && value < p->h.nsub && p->h.split)
+        return fail(p, PSATD_E_INVALID, "the split x/y passes do not batch");
       HIPCHK(p, hipStreamSynchronize(p->stream));
       set_batches(p->h, value);
       d.slab = p->h.batch_slab;
@@ -512,9 +558,32 @@ psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
       if (value != 0 && value != 1) return fail(p, PSATD_E_INVALID, "xcd remap must be 0 or 1");
       d.xcd = value;
       break;
+    case PSATD_TUNE_MAX_RADIX: {
+      if (value != 8 && value != 16) return fail(p, PSATD_E_INVALID, "max radix must be 8 or 16");
+      HostTables trial = p->h;
+      if (!set_max_radix(trial, value))
+        return fail(p, PSATD_E_INVALID, "a padded length has no schedule with this max radix");
+      HIPCHK(p, hipStreamSynchronize(p->stream));
+      HIPCHK(p, hipMemcpy(const_cast<FftPlanD*>(d.plans), trial.plans.data(),
+                          trial.plans.size() * sizeof(FftPlanD), hipMemcpyHostToDevice));
+      p->h.plans = trial.plans;
+      p->h.maxr = value;
+      d.maxr = value;
+      break;
+    }
+    case PSATD_TUNE_XY_THREADS:
+      if (value != 256 && value != 512) return fail(p, PSATD_E_INVALID, "x/y threads must be 256 or 512");
+      p->h.ntxy = value;
+      d.ntxy = value;
+      break;
+    case PSATD_TUNE_Z_THREADS:
+      if (value != 512 && value != 1024) return fail(p, PSATD_E_INVALID, "z threads must be 512 or 1024");
+      p->h.ntu = value;
+      d.ntu = value;
+      break;
     default: {
       if (value < 0) return fail(p, PSATD_E_INVALID, "grid size must be >= 0");
-      static const int phase_of[] = {0, 0, kPhaseFwd, kPhaseUpd, kPhaseInv, kPhaseExchEB, 0};
+      static const int phase_of[] = {0, 0, kPhaseFwd, kPhaseUpd, kPhaseInv, kPhaseExchEB, 0, 0, 0, 0, 0};
       d.grid_cap[phase_of[key]] = value;
       if (key == PSATD_TUNE_GRID_EXCH) d.grid_cap[kPhaseExchJ] = value;
     }
@@ -528,6 +597,99 @@ psatd_status psatd_get_tuning(psatd_plan_t p, int32_t key, int32_t* value) {
   if (!p || !value) return fail(p, PSATD_E_INVALID, "null argument");
   if (key < 0 || key >= PSATD_NTUNE) return fail(p, PSATD_E_INVALID, "unknown tuning key");
   *value = p->tune[key];
+  return PSATD_OK;
+}
+
+namespace {
+
+// Mean ms per step of each phase over nsteps (psatd_run_profiled without the
+// argument checks).
+psatd_status time_phases(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3], int nsteps,
+                         double* ms) {
+  return psatd_run_profiled(p, E, B, J, nsteps, ms);
+}
+
+std::string tune_key(psatd_plan_t p) {
+  hipDeviceProp_t prop;
+  std::string dev = "gpu";
+  if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) dev = prop.gcnArchName;
+  for (char& ch : dev)
+    if (ch == ' ' || ch == ':') ch = '_';
+  std::map<std::string, int> shapes;
+  for (const BoxD& b : p->h.box)
+    shapes[std::to_string(b.P[0]) + "x" + std::to_string(b.P[1]) + "x" + std::to_string(b.P[2])]++;
+  std::ostringstream k;
+  k << dev << "|prec" << p->h.prec << "|batch" << p->h.batch_boxes << "|";
+  for (auto& kv : shapes) k << kv.first << "*" << kv.second << ",";
+  return k.str();
+}
+
+}  // namespace
+
+psatd_status psatd_autotune(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3],
+                            int32_t steps, const char* cache_path, double* best_ms) {
+  psatd_status r = check_step_args(p, E, B, J);
+  if (r != PSATD_OK) return r;
+  if (steps < 1) return fail(p, PSATD_E_INVALID, "steps_per_trial < 1");
+  const std::string key = tune_key(p);
+  static const int keys[] = {PSATD_TUNE_MAX_RADIX, PSATD_TUNE_XY_THREADS, PSATD_TUNE_Z_PENCILS,
+                             PSATD_TUNE_Z_THREADS, PSATD_TUNE_XCD_REMAP};
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      std::istringstream ls(line);
+      std::string k;
+      int v[5];
+      if (!(ls >> k >> v[0] >> v[1] >> v[2] >> v[3] >> v[4]) || k != key) continue;
+      for (int i = 0; i < 5; ++i)
+        if ((r = psatd_set_tuning(p, keys[i], v[i])) != PSATD_OK) return r;
+      if (best_ms) *best_ms = 0.0;
+      return PSATD_OK;
+    }
+  }
+  // Phases are separate kernels: the x/y shape and the z shape are tuned
+  // independently for each largest radix (which both share).
+  double best_total = 1e300;
+  int best[5] = {p->tune[PSATD_TUNE_MAX_RADIX], p->tune[PSATD_TUNE_XY_THREADS], p->tune[PSATD_TUNE_Z_PENCILS],
+                 p->tune[PSATD_TUNE_Z_THREADS], p->tune[PSATD_TUNE_XCD_REMAP]};
+  double ms[kNumPhases];
+  for (int maxr : {16, 8}) {
+    if (psatd_set_tuning(p, PSATD_TUNE_MAX_RADIX, maxr) != PSATD_OK) continue;
+    double bxy = 1e300, bz = 1e300, other = 0.0;
+    int cxy = 256, cpb = p->h.PB, czt = 512, cx = 1;
+    for (int xcd : {1, 0}) {
+      if ((r = psatd_set_tuning(p, PSATD_TUNE_XCD_REMAP, xcd)) != PSATD_OK) return r;
+      for (int xy : {256, 512}) {
+        if ((r = psatd_set_tuning(p, PSATD_TUNE_XY_THREADS, xy)) != PSATD_OK) return r;
+        for (int pb : {16, 8}) {
+          if (psatd_set_tuning(p, PSATD_TUNE_Z_PENCILS, pb) != PSATD_OK) continue;
+          for (int zt : {512, 1024}) {
+            if ((r = psatd_set_tuning(p, PSATD_TUNE_Z_THREADS, zt)) != PSATD_OK) return r;
+            if ((r = time_phases(p, E, B, J, 1, ms)) != PSATD_OK) return r;  // warm-up
+            if ((r = time_phases(p, E, B, J, steps, ms)) != PSATD_OK) return r;
+            const double txy = ms[kPhaseFwd] + ms[kPhaseInv];
+            const double tz = ms[kPhaseUpd];
+            if (txy < bxy) { bxy = txy; cxy = xy; cx = xcd; }
+            if (tz < bz) { bz = tz; cpb = pb; czt = zt; }
+            other = ms[kPhaseExchJ] + ms[kPhaseExchEB];
+          }
+        }
+      }
+    }
+    const double total = bxy + bz + other;
+    if (total < best_total) {
+      best_total = total;
+      best[0] = maxr; best[1] = cxy; best[2] = cpb; best[3] = czt; best[4] = cx;
+    }
+  }
+  for (int i = 0; i < 5; ++i)
+    if ((r = psatd_set_tuning(p, keys[i], best[i])) != PSATD_OK) return r;
+  if (best_ms) *best_ms = best_total;
+  if (cache_path) {
+    std::ofstream out(cache_path, std::ios::app);
+    if (out) out << key << " " << best[0] << " " << best[1] << " " << best[2] << " " << best[3] << " " << best[4] << "\n";
+  }
   return PSATD_OK;
 }
 

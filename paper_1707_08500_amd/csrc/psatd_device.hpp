@@ -13,6 +13,7 @@ namespace psatd {
 
 // Launch shapes (gfx950: 64-wide waves, 160 KiB LDS per compute unit).
 constexpr int kThreadsXY = 256;   // x/y plane passes, exchange, scatter/gather
+constexpr int kMaxR = 16;         // largest radix codelet (radix 11 is always available)
 constexpr int kMaxDynLds = 160 * 1024;
 
 // One padded subdomain (Sec. 3.2, Fig. 2a).  Axes (x, y, z).
@@ -101,7 +102,7 @@ struct FwdArgs {
 
 // LDS: the plane [y][x] with row stride ld, then the twiddles of the x plan
 // (Nh), the y plan (Py) and W_Px (real <-> half spectrum).
-template <typename T, class Bar>
+template <typename T, int MAXR, class Bar>
 PSATD_HD void body_fwd_xy(const FwdArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar) {
   const int s = find_box(a.items, a.t.nsub, item);
   const BoxD& bx = a.t.box[s];
@@ -115,10 +116,18 @@ PSATD_HD void body_fwd_xy(const FwdArgs<T>& a, int item, int tid, int nt, cx<T>*
   cx<T>* twx = lds + Py * ld;
   cx<T>* twy = twx + Nh;
   cx<T>* twr = twy + Py;
+  int32_t* posx = reinterpret_cast<int32_t*>(twr + Px);
+  int32_t* posy = posx + Nh;
   const cx<T>* gtx = a.t.tw + plx->tw;
   const cx<T>* gty = a.t.tw + ply->tw;
   const cx<T>* gtr = a.t.tw + bx.twr;
 
+  // stage-digit positions along x (input of the dit) and y (output of the dif)
+  for (int i = tid; i < Nh + Py; i += nt) {
+    if (i < Nh) posx[i] = plan_pos(plx, i);
+    else posy[i - Nh] = plan_pos(ply, i - Nh);
+  }
+  bar();
   // packed real rows (x natural) -> LDS rows in stage-digit order along x,
   // together with the three twiddle tables
   const cx<T>* src = reinterpret_cast<const cx<T>*>(a.in[f] + bx.foff + (int64_t)z * Py * Px);
@@ -133,13 +142,13 @@ PSATD_HD void body_fwd_xy(const FwdArgs<T>& a, int item, int tid, int nt, cx<T>*
                          [&](int i, cx<T> v) {
                            if (i < nplane) {
                              const int y = (int)fdiv((uint32_t)i, dNh);
-                             lds[y * ld + plan_pos(plx, i - y * Nh)] = v;
+                             lds[y * ld + posx[i - y * Nh]] = v;
                            } else {
                              twx[i - nplane] = v;  // twx, twy, twr are contiguous
                            }
                          });
   bar();
-  fft_dit<-1>(lds, Py, ld, 1, plx, twx, tid, nt, bar);
+  fft_dit<-1, MAXR>(lds, Py, ld, 1, plx, twx, tid, nt, bar);
   const int np = Nh / 2 + 1;
   const FastDiv dnp = make_fastdiv((uint32_t)np);
   for (int i = tid; i < Py * np; i += nt) {
@@ -147,13 +156,13 @@ PSATD_HD void body_fwd_xy(const FwdArgs<T>& a, int item, int tid, int nt, cx<T>*
     r2c_post(lds + y * ld, i - y * np, Nh, twr);
   }
   bar();
-  fft_dif<-1>(lds, H, 1, ld, ply, twy, tid, nt, bar);
+  fft_dif<-1, MAXR>(lds, H, 1, ld, ply, twy, tid, nt, bar);
   cx<T>* dst = a.spec + f * a.slab + (bx.soff - a.sbias) + (int64_t)z * Py * H;
   const FastDiv dH = make_fastdiv((uint32_t)H);
   copy_batched<8, cx<T>>(Py * H, tid, nt,
                          [&](int i) {
                            const int ky = (int)fdiv((uint32_t)i, dH);
-                           return lds[plan_pos(ply, ky) * ld + (i - ky * H)];
+                           return lds[posy[ky] * ld + (i - ky * H)];
                          },
                          [&](int i, cx<T> v) { dst[i] = v; });
 }
@@ -165,7 +174,7 @@ struct UpdConst {
   double c, dt;
 };
 
-// Eqs. PSATD_1 / PSATD_2 (general c) at one k-point, FP64 arithmetic.
+// Eqs. PSATD_1 / PSATD_2 (general c) at one k-point; coefficients in FP64.
 //   E' = C E + i c^2 (S/ck) [k]xB - (S/ck) J + X1 [k]([k].E) + X2 [k]([k].J)
 //   B' = C B - i (S/ck) [k]xE + i (X1/c^2) [k]xJ
 // C = cos th, S = sin th, th = c|[k]|dt, X1 = (1-C)/|[k]|^2 = 2 sin^2(th/2)/|[k]|^2,
@@ -201,36 +210,38 @@ PSATD_HD void psatd_point(T* vr, T* vi /* E0 E1 E2 B0 B1 B2 J0 J1 J2 */, double 
       X2 = (Sck - dt) / k2;
     }
   }
-  double er[3], ei[3], br[3], bi[3], jr[3], ji[3];
+  // The coefficients are FP64; the multiply-adds run in the state's type T
+  // (FP64 path: double; FP32 path: float, where they act on increments).
+  T er[3], ei[3], br[3], bi[3], jr[3], ji[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    er[a] = (double)vr[a]; ei[a] = (double)vi[a];
-    br[a] = (double)vr[3 + a]; bi[a] = (double)vi[3 + a];
-    jr[a] = (double)vr[6 + a]; ji[a] = (double)vi[6 + a];
+    er[a] = vr[a]; ei[a] = vi[a];
+    br[a] = vr[3 + a]; bi[a] = vi[3 + a];
+    jr[a] = vr[6 + a]; ji[a] = vi[6 + a];
   }
-  const double K[3] = {kx, ky, kz};
-  const double kEr = kx * er[0] + ky * er[1] + kz * er[2];
-  const double kEi = kx * ei[0] + ky * ei[1] + kz * ei[2];
-  const double kJr = kx * jr[0] + ky * jr[1] + kz * jr[2];
-  const double kJi = kx * ji[0] + ky * ji[1] + kz * ji[2];
+  const T tkx = (T)kx, tky = (T)ky, tkz = (T)kz;
+  const T K[3] = {tkx, tky, tkz};
+  const T tC = (T)C, tS = (T)Sck, tX1 = (T)X1, tX2 = (T)X2;
+  const T a1 = (T)(c2 * Sck);
+  const T x1c = (T)(X1 / c2);
+  const T kEr = tkx * er[0] + tky * er[1] + tkz * er[2];
+  const T kEi = tkx * ei[0] + tky * ei[1] + tkz * ei[2];
+  const T kJr = tkx * jr[0] + tky * jr[1] + tkz * jr[2];
+  const T kJi = tkx * ji[0] + tky * ji[1] + tkz * ji[2];
   // cross products [k] x F, real and imaginary parts
-  const double kxBr[3] = {ky * br[2] - kz * br[1], kz * br[0] - kx * br[2], kx * br[1] - ky * br[0]};
-  const double kxBi[3] = {ky * bi[2] - kz * bi[1], kz * bi[0] - kx * bi[2], kx * bi[1] - ky * bi[0]};
-  const double kxEr[3] = {ky * er[2] - kz * er[1], kz * er[0] - kx * er[2], kx * er[1] - ky * er[0]};
-  const double kxEi[3] = {ky * ei[2] - kz * ei[1], kz * ei[0] - kx * ei[2], kx * ei[1] - ky * ei[0]};
-  const double kxJr[3] = {ky * jr[2] - kz * jr[1], kz * jr[0] - kx * jr[2], kx * jr[1] - ky * jr[0]};
-  const double kxJi[3] = {ky * ji[2] - kz * ji[1], kz * ji[0] - kx * ji[2], kx * ji[1] - ky * ji[0]};
-  const double a1 = c2 * Sck;
-  const double x1c = X1 / c2;
+  const T kxBr[3] = {tky * br[2] - tkz * br[1], tkz * br[0] - tkx * br[2], tkx * br[1] - tky * br[0]};
+  const T kxBi[3] = {tky * bi[2] - tkz * bi[1], tkz * bi[0] - tkx * bi[2], tkx * bi[1] - tky * bi[0]};
+  const T kxEr[3] = {tky * er[2] - tkz * er[1], tkz * er[0] - tkx * er[2], tkx * er[1] - tky * er[0]};
+  const T kxEi[3] = {tky * ei[2] - tkz * ei[1], tkz * ei[0] - tkx * ei[2], tkx * ei[1] - tky * ei[0]};
+  const T kxJr[3] = {tky * jr[2] - tkz * jr[1], tkz * jr[0] - tkx * jr[2], tkx * jr[1] - tky * jr[0]};
+  const T kxJi[3] = {tky * ji[2] - tkz * ji[1], tkz * ji[0] - tkx * ji[2], tkx * ji[1] - tky * ji[0]};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     // i * z = (-z.i, z.r)
-    const double Er = C * er[a] - a1 * kxBi[a] - Sck * jr[a] + X1 * K[a] * kEr + X2 * K[a] * kJr;
-    const double Ei = C * ei[a] + a1 * kxBr[a] - Sck * ji[a] + X1 * K[a] * kEi + X2 * K[a] * kJi;
-    const double Br = C * br[a] + Sck * kxEi[a] - x1c * kxJi[a];
-    const double Bi = C * bi[a] - Sck * kxEr[a] + x1c * kxJr[a];
-    vr[a] = (T)Er; vi[a] = (T)Ei;
-    vr[3 + a] = (T)Br; vi[3 + a] = (T)Bi;
+    vr[a] = tC * er[a] - a1 * kxBi[a] - tS * jr[a] + tX1 * K[a] * kEr + tX2 * K[a] * kJr;
+    vi[a] = tC * ei[a] + a1 * kxBr[a] - tS * ji[a] + tX1 * K[a] * kEi + tX2 * K[a] * kJi;
+    vr[3 + a] = tC * br[a] + tS * kxEi[a] - x1c * kxJi[a];
+    vi[3 + a] = tC * bi[a] - tS * kxEr[a] + x1c * kxJr[a];
   }
 }
 
@@ -248,7 +259,7 @@ struct UpdArgs {
 // [z][f * PB + p] (W = 9 PB complex per z row), so that all 9 (then the 6
 // output) fields are transformed by one multi-transform pass with a uniform
 // element stride W.  Pencils past the end of the box (last block) are zeros.
-template <typename T, int PB, bool INC, class Bar>
+template <typename T, int PB, bool INC, int MAXR, class Bar>
 PSATD_HD void body_z_update(const UpdArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar) {
   const int s = find_box(a.items, a.t.nsub, item);
   const BoxD& bx = a.t.box[s];
@@ -260,7 +271,9 @@ PSATD_HD void body_z_update(const UpdArgs<T>& a, int item, int tid, int nt, cx<T
   const FftPlanD* plz = a.t.plans + bx.planz;
   constexpr int W = 9 * PB;
   cx<T>* twz = lds + Pz * W;
+  int32_t* kzi = reinterpret_cast<int32_t*>(twz + Pz);  // frequency at each z slot
   const cx<T>* gtz = a.t.tw + plz->tw;
+  for (int i = tid; i < Pz; i += nt) kzi[i] = plan_index(plz, i);
   const cx<T>* src = a.spec + (bx.soff - a.sbias) + q0;
   const int64_t slab = a.slab;
   const FastDiv dPz = make_fastdiv((uint32_t)Pz);
@@ -287,7 +300,7 @@ PSATD_HD void body_z_update(const UpdArgs<T>& a, int item, int tid, int nt, cx<T
         lds[z * W + f * PB + p] = v;
       });
   bar();
-  fft_dif<-1>(lds, 9 * PB, 1, W, plz, twz, tid, nt, bar);
+  fft_dif<-1, MAXR>(lds, 9 * PB, 1, W, plz, twz, tid, nt, bar);
 
   const double* kxt = a.t.kmod + bx.kx;
   const double* kyt = a.t.kmod + bx.ky;
@@ -308,12 +321,12 @@ PSATD_HD void body_z_update(const UpdArgs<T>& a, int item, int tid, int nt, cx<T
     const int q = q0 + p;
     const int ky = (int)fdiv((uint32_t)q, dH);
     const int kx = q - ky * H;
-    psatd_point<T, INC>(vr, vi, kxt[kx], kyt[ky], kzt[plan_index(plz, slot)], a.k.c, a.k.dt);
+    psatd_point<T, INC>(vr, vi, kxt[kx], kyt[ky], kzt[kzi[slot]], a.k.c, a.k.dt);
 #pragma unroll
     for (int f = 0; f < 6; ++f) row[f * PB] = cx<T>{vr[f], vi[f]};
   }
   bar();
-  fft_dit<+1>(lds, 6 * PB, 1, W, plz, twz, tid, nt, bar);
+  fft_dit<+1, MAXR>(lds, 6 * PB, 1, W, plz, twz, tid, nt, bar);
 
   cx<T>* dst = a.spec + (bx.soff - a.sbias) + q0;
   copy_batched<8, cx<T>>(6 * Pz * PB, tid, nt,
@@ -350,7 +363,7 @@ struct InvArgs {
 
 // LDS: the plane with row stride ld, then the twiddles of the y plan (Py),
 // the x plan (Nh) and W_Px.
-template <typename T, bool INC, class Bar>
+template <typename T, bool INC, int MAXR, class Bar>
 PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar) {
   const int s = find_box(a.items, a.t.nsub, item);
   const BoxD& bx = a.t.box[s];
@@ -365,9 +378,18 @@ PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>*
   cx<T>* twy = lds + Py * ld;
   cx<T>* twx = twy + Py;
   cx<T>* twr = twx + Nh;
+  int32_t* posy = reinterpret_cast<int32_t*>(twr + Px);
+  int32_t* posx = posy + Py;
   const cx<T>* gty = a.t.tw + ply->tw;
   const cx<T>* gtx = a.t.tw + plx->tw;
   const cx<T>* gtr = a.t.tw + bx.twr;
+
+  // stage-digit positions along y (input of the dit) and x (output of the dif)
+  for (int i = tid; i < Py + Nh; i += nt) {
+    if (i < Py) posy[i] = plan_pos(ply, i);
+    else posx[i - Py] = plan_pos(plx, i - Py);
+  }
+  bar();
 
   // half-spectrum rows (ky natural) -> LDS rows in stage-digit order along y
   const cx<T>* src = a.spec + f * a.slab + (bx.soff - a.sbias) + (int64_t)z * Py * H;
@@ -382,13 +404,13 @@ PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>*
                          [&](int i, cx<T> v) {
                            if (i < nplane) {
                              const int ky = (int)fdiv((uint32_t)i, dH);
-                             lds[plan_pos(ply, ky) * ld + (i - ky * H)] = v;
+                             lds[posy[ky] * ld + (i - ky * H)] = v;
                            } else {
                              twy[i - nplane] = v;  // twy, twx, twr are contiguous
                            }
                          });
   bar();
-  fft_dit<+1>(lds, H, 1, ld, ply, twy, tid, nt, bar);
+  fft_dit<+1, MAXR>(lds, H, 1, ld, ply, twy, tid, nt, bar);
   const int ny = bx.n[1], gy = bx.g[1];
   const int np = Nh / 2 + 1;
   const FastDiv dnp = make_fastdiv((uint32_t)np);
@@ -397,7 +419,7 @@ PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>*
     c2r_pre(lds + (gy + y) * ld, i - y * np, Nh, twr);
   }
   bar();
-  fft_dif<+1>(lds + gy * ld, ny, ld, 1, plx, twx, tid, nt, bar);
+  fft_dif<+1, MAXR>(lds + gy * ld, ny, ld, 1, plx, twx, tid, nt, bar);
   // 1/V applied in FP64 and rounded once: an FP32 1/V (not a power of two for
   // most V) would bias every step by the same relative amount.
   const double sc = 1.0 / ((double)Px * (double)Py * (double)Pz);
@@ -408,13 +430,213 @@ PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>*
                      [&](int i) {
                        const int yy = (int)fdiv((uint32_t)i, dnx);
                        const int x = gx + (i - yy * nx);
-                       const cx<T> v = lds[(gy + yy) * ld + plan_pos(plx, x >> 1)];
+                       const cx<T> v = lds[(gy + yy) * ld + posx[x >> 1]];
                        return (T)((double)((x & 1) ? v.y : v.x) * sc);
                      },
                      [&](int i, T v) {
                        const int yy = (int)fdiv((uint32_t)i, dnx);
                        T* q = dst + (gy + yy) * Px + gx + (i - yy * nx);
                        *q = INC ? *q + v : v;  // INC: v is the increment
+                     });
+}
+
+// ------------------------------------------------ split x / y passes
+// For padded planes larger than the LDS the x/y pass is split: x rows and y
+// columns are transformed by separate work items through the workspace
+// (natural order in memory between the two).  RB rows / CB columns per item.
+constexpr int kRB = 16;
+constexpr int kCB = 16;
+
+template <typename T>
+struct SplitArgs {
+  Tables<T> t;
+  const int32_t* items;
+  const T* in[9];      // x forward: field inputs
+  T* out[6];           // x inverse: field outputs
+  cx<T>* spec;
+  int64_t slab;
+  int64_t sbias;
+};
+
+// x forward: kRB rows of (box, z, field): packed real rows -> half spectrum rows.
+template <typename T, int MAXR, class Bar>
+PSATD_HD void body_x_fwd(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar) {
+  const int s = find_box(a.items, a.t.nsub, item);
+  const BoxD& bx = a.t.box[s];
+  const int Px = bx.P[0], Py = bx.P[1], Pz = bx.P[2];
+  const int nrb = (Py + kRB - 1) / kRB;
+  const int local = item - a.items[s];
+  const int f = local / (Pz * nrb);
+  const int r = local - f * Pz * nrb;
+  const int z = r / nrb;
+  const int y0 = (r - z * nrb) * kRB;
+  const int ny = (Py - y0) < kRB ? (Py - y0) : kRB;
+  const int Nh = Px >> 1, H = bx.H, ld = bx.ld;
+  const FftPlanD* plx = a.t.plans + bx.planx;
+  cx<T>* twx = lds + kRB * ld;
+  cx<T>* twr = twx + Nh;
+  int32_t* posx = reinterpret_cast<int32_t*>(twr + Px);
+  for (int i = tid; i < Nh; i += nt) posx[i] = plan_pos(plx, i);
+  bar();
+  const cx<T>* src = reinterpret_cast<const cx<T>*>(a.in[f] + bx.foff + ((int64_t)z * Py + y0) * Px);
+  const cx<T>* gtx = a.t.tw + plx->tw;
+  const cx<T>* gtr = a.t.tw + bx.twr;
+  const int nrow = ny * Nh;
+  const FastDiv dNh = make_fastdiv((uint32_t)Nh);
+  copy_batched<8, cx<T>>(nrow + Nh + Px, tid, nt,
+                         [&](int i) {
+                           if (i < nrow) return src[i];
+                           const int j = i - nrow;
+                           return j < Nh ? gtx[j] : gtr[j - Nh];
+                         },
+                         [&](int i, cx<T> v) {
+                           if (i < nrow) {
+                             const int y = (int)fdiv((uint32_t)i, dNh);
+                             lds[y * ld + posx[i - y * Nh]] = v;
+                           } else {
+                             twx[i - nrow] = v;  // twx, twr contiguous
+                           }
+                         });
+  bar();
+  fft_dit<-1, MAXR>(lds, ny, ld, 1, plx, twx, tid, nt, bar);
+  const int np = Nh / 2 + 1;
+  const FastDiv dnp = make_fastdiv((uint32_t)np);
+  for (int i = tid; i < ny * np; i += nt) {
+    const int y = (int)fdiv((uint32_t)i, dnp);
+    r2c_post(lds + y * ld, i - y * np, Nh, twr);
+  }
+  bar();
+  cx<T>* dst = a.spec + f * a.slab + (bx.soff - a.sbias) + ((int64_t)z * Py + y0) * H;
+  const FastDiv dH = make_fastdiv((uint32_t)H);
+  copy_batched<8, cx<T>>(ny * H, tid, nt,
+                         [&](int i) {
+                           const int y = (int)fdiv((uint32_t)i, dH);
+                           return lds[y * ld + (i - y * H)];
+                         },
+                         [&](int i, cx<T> v) { dst[i] = v; });
+}
+
+// y columns: kCB half-spectrum columns of (box, z, field), in place in the
+// workspace; DIR -1: forward over all planes and 9 fields; +1: inverse over
+// interior planes and the 6 outputs.
+template <typename T, int DIR, int MAXR, class Bar>
+PSATD_HD void body_y(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar) {
+  const int s = find_box(a.items, a.t.nsub, item);
+  const BoxD& bx = a.t.box[s];
+  const int Py = bx.P[1], H = bx.H;
+  const int ncb = (H + kCB - 1) / kCB;
+  const int nzp = DIR < 0 ? bx.P[2] : bx.n[2];
+  const int local = item - a.items[s];
+  const int f = local / (nzp * ncb);
+  const int r = local - f * nzp * ncb;
+  const int zz = r / ncb;
+  const int z = DIR < 0 ? zz : bx.g[2] + zz;
+  const int c0 = (r - zz * ncb) * kCB;
+  const int nc = (H - c0) < kCB ? (H - c0) : kCB;
+  const FftPlanD* ply = a.t.plans + bx.plany;
+  cx<T>* twy = lds + Py * kCB;
+  int32_t* posy = reinterpret_cast<int32_t*>(twy + Py);
+  for (int i = tid; i < Py; i += nt) posy[i] = plan_pos(ply, i);
+  bar();
+  cx<T>* col = a.spec + f * a.slab + (bx.soff - a.sbias) + (int64_t)z * Py * H + c0;
+  const cx<T>* gty = a.t.tw + ply->tw;
+  const int ntot = Py * kCB;
+  copy_batched<8, cx<T>>(ntot + Py, tid, nt,
+                         [&](int i) {
+                           if (i >= ntot) return gty[i - ntot];
+                           const int y = i / kCB, c = i % kCB;
+                           return c < nc ? col[(int64_t)y * H + c] : cx<T>{T(0), T(0)};
+                         },
+                         [&](int i, cx<T> v) {
+                           if (i >= ntot) {
+                             twy[i - ntot] = v;
+                             return;
+                           }
+                           const int y = i / kCB, c = i % kCB;
+                           lds[(DIR < 0 ? y : posy[y]) * kCB + c] = v;
+                         });
+  bar();
+  if (DIR < 0)
+    fft_dif<-1, MAXR>(lds, nc, 1, kCB, ply, twy, tid, nt, bar);
+  else
+    fft_dit<+1, MAXR>(lds, nc, 1, kCB, ply, twy, tid, nt, bar);
+  copy_batched<8, cx<T>>(ntot, tid, nt,
+                         [&](int i) {
+                           const int y = i / kCB, c = i % kCB;
+                           return lds[(DIR < 0 ? posy[y] : y) * kCB + c];
+                         },
+                         [&](int i, cx<T> v) {
+                           const int y = i / kCB, c = i % kCB;
+                           if (c < nc) col[(int64_t)y * H + c] = v;
+                         });
+}
+
+// x inverse: kRB interior rows of (box, interior z, output field):
+// half spectrum rows -> real rows, interior cells written (INC: added).
+template <typename T, bool INC, int MAXR, class Bar>
+PSATD_HD void body_x_inv(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar) {
+  const int s = find_box(a.items, a.t.nsub, item);
+  const BoxD& bx = a.t.box[s];
+  const int Px = bx.P[0], Py = bx.P[1], Pz = bx.P[2];
+  const int nyi = bx.n[1], nz = bx.n[2];
+  const int nrb = (nyi + kRB - 1) / kRB;
+  const int local = item - a.items[s];
+  const int f = local / (nz * nrb);
+  const int r = local - f * nz * nrb;
+  const int zz = r / nrb;
+  const int z = bx.g[2] + zz;
+  const int yy0 = (r - zz * nrb) * kRB;
+  const int ny = (nyi - yy0) < kRB ? (nyi - yy0) : kRB;
+  const int y0 = bx.g[1] + yy0;
+  const int Nh = Px >> 1, H = bx.H, ld = bx.ld;
+  const FftPlanD* plx = a.t.plans + bx.planx;
+  cx<T>* twx = lds + kRB * ld;
+  cx<T>* twr = twx + Nh;
+  int32_t* posx = reinterpret_cast<int32_t*>(twr + Px);
+  for (int i = tid; i < Nh; i += nt) posx[i] = plan_pos(plx, i);
+  const cx<T>* src = a.spec + f * a.slab + (bx.soff - a.sbias) + ((int64_t)z * Py + y0) * H;
+  const cx<T>* gtx = a.t.tw + plx->tw;
+  const cx<T>* gtr = a.t.tw + bx.twr;
+  const int nrow = ny * H;
+  const FastDiv dH = make_fastdiv((uint32_t)H);
+  copy_batched<8, cx<T>>(nrow + Nh + Px, tid, nt,
+                         [&](int i) {
+                           if (i < nrow) return src[i];
+                           const int j = i - nrow;
+                           return j < Nh ? gtx[j] : gtr[j - Nh];
+                         },
+                         [&](int i, cx<T> v) {
+                           if (i < nrow) {
+                             const int y = (int)fdiv((uint32_t)i, dH);
+                             lds[y * ld + (i - y * H)] = v;
+                           } else {
+                             twx[i - nrow] = v;
+                           }
+                         });
+  bar();
+  const int np = Nh / 2 + 1;
+  const FastDiv dnp = make_fastdiv((uint32_t)np);
+  for (int i = tid; i < ny * np; i += nt) {
+    const int y = (int)fdiv((uint32_t)i, dnp);
+    c2r_pre(lds + y * ld, i - y * np, Nh, twr);
+  }
+  bar();
+  fft_dif<+1, MAXR>(lds, ny, ld, 1, plx, twx, tid, nt, bar);
+  const double sc = 1.0 / ((double)Px * (double)Py * (double)Pz);
+  const int nx = bx.n[0], gx = bx.g[0];
+  T* dst = a.out[f] + bx.foff + ((int64_t)z * Py + y0) * Px;
+  const FastDiv dnx = make_fastdiv((uint32_t)nx);
+  copy_batched<8, T>(ny * nx, tid, nt,
+                     [&](int i) {
+                       const int y = (int)fdiv((uint32_t)i, dnx);
+                       const int x = gx + (i - y * nx);
+                       const cx<T> v = lds[y * ld + posx[x >> 1]];
+                       return (T)((double)((x & 1) ? v.y : v.x) * sc);
+                     },
+                     [&](int i, T v) {
+                       const int y = (int)fdiv((uint32_t)i, dnx);
+                       T* q = dst + y * Px + gx + (i - y * nx);
+                       *q = INC ? *q + v : v;
                      });
 }
 

@@ -29,29 +29,56 @@ __device__ __forceinline__ int first_item(int remap) {
   return b;
 }
 
-template <typename T>
-__global__ __launch_bounds__(kThreadsXY) void k_fwd_xy(FwdArgs<T> a, int item0, int nitems, int remap) {
+template <typename T, int NT, int MAXR>
+__global__ __launch_bounds__(NT) void k_fwd_xy(FwdArgs<T> a, int item0, int nitems, int remap) {
   cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
   for (int it = first_item(remap); it < nitems; it += gridDim.x) {
-    body_fwd_xy(a, item0 + it, threadIdx.x, blockDim.x, lds, BlockBarrier{});
+    body_fwd_xy<T, MAXR>(a, item0 + it, threadIdx.x, NT, lds, BlockBarrier{});
     __syncthreads();
   }
 }
 
-template <typename T, bool INC>
-__global__ __launch_bounds__(kThreadsXY) void k_inv_xy(InvArgs<T> a, int item0, int nitems, int remap) {
+template <typename T, bool INC, int NT, int MAXR>
+__global__ __launch_bounds__(NT) void k_inv_xy(InvArgs<T> a, int item0, int nitems, int remap) {
   cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
   for (int it = first_item(remap); it < nitems; it += gridDim.x) {
-    body_inv_xy<T, INC>(a, item0 + it, threadIdx.x, blockDim.x, lds, BlockBarrier{});
+    body_inv_xy<T, INC, MAXR>(a, item0 + it, threadIdx.x, NT, lds, BlockBarrier{});
     __syncthreads();
   }
 }
 
-template <typename T, int NT, int PB, bool INC>
+template <typename T, int NT, int PB, bool INC, int MAXR>
 __global__ __launch_bounds__(NT) void k_z_update(UpdArgs<T> a, int item0, int nitems, int remap) {
   cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
   for (int it = first_item(remap); it < nitems; it += gridDim.x) {
-    body_z_update<T, PB, INC>(a, item0 + it, threadIdx.x, NT, lds, BlockBarrier{});
+    body_z_update<T, PB, INC, MAXR>(a, item0 + it, threadIdx.x, NT, lds, BlockBarrier{});
+    __syncthreads();
+  }
+}
+
+template <typename T, int MAXR>
+__global__ __launch_bounds__(kThreadsXY) void k_x_fwd(SplitArgs<T> a, int nitems, int remap) {
+  cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
+  for (int it = first_item(remap); it < nitems; it += gridDim.x) {
+    body_x_fwd<T, MAXR>(a, it, threadIdx.x, kThreadsXY, lds, BlockBarrier{});
+    __syncthreads();
+  }
+}
+
+template <typename T, int DIR, int MAXR>
+__global__ __launch_bounds__(kThreadsXY) void k_y(SplitArgs<T> a, int nitems, int remap) {
+  cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
+  for (int it = first_item(remap); it < nitems; it += gridDim.x) {
+    body_y<T, DIR, MAXR>(a, it, threadIdx.x, kThreadsXY, lds, BlockBarrier{});
+    __syncthreads();
+  }
+}
+
+template <typename T, bool INC, int MAXR>
+__global__ __launch_bounds__(kThreadsXY) void k_x_inv(SplitArgs<T> a, int nitems, int remap) {
+  cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
+  for (int it = first_item(remap); it < nitems; it += gridDim.x) {
+    body_x_inv<T, INC, MAXR>(a, it, threadIdx.x, kThreadsXY, lds, BlockBarrier{});
     __syncthreads();
   }
 }
@@ -109,31 +136,39 @@ static Tables<T> tables(const DevPlan& p) {
 // The FP32 path transforms increments (INC), the FP64 path the new fields.
 template <typename T> struct IncOf { static constexpr bool value = sizeof(T) == 4; };
 
-template <typename T>
-static hipError_t set_upd_attr(int lds) {
-  constexpr bool I = IncOf<T>::value;
-  const void* fns[] = {
-      (const void*)k_z_update<T, 512, 2, I>,  (const void*)k_z_update<T, 512, 4, I>,
-      (const void*)k_z_update<T, 512, 8, I>,  (const void*)k_z_update<T, 512, 16, I>,
-      (const void*)k_z_update<T, 1024, 2, I>, (const void*)k_z_update<T, 1024, 4, I>,
-      (const void*)k_z_update<T, 1024, 8, I>, (const void*)k_z_update<T, 1024, 16, I>};
-  for (const void* f : fns) {
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+static hipError_t set_lds(const void* f, int lds) {
+  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
-hipError_t prepare_kernels(bool f64, int ldsF, int ldsI, int ldsU) {
+template <typename T, int MAXR>
+static hipError_t prepare_t(int ldsF, int ldsI, int ldsU, int ldsX, int ldsY) {
+  constexpr bool I = IncOf<T>::value;
+  const void* xy[] = {(const void*)k_fwd_xy<T, 256, MAXR>, (const void*)k_fwd_xy<T, 512, MAXR>};
+  const void* inv[] = {(const void*)k_inv_xy<T, I, 256, MAXR>, (const void*)k_inv_xy<T, I, 512, MAXR>};
+  const void* upd[] = {(const void*)k_z_update<T, 512, 8, I, MAXR>, (const void*)k_z_update<T, 512, 16, I, MAXR>,
+                       (const void*)k_z_update<T, 1024, 8, I, MAXR>, (const void*)k_z_update<T, 1024, 16, I, MAXR>,
+                       (const void*)k_z_update<T, 512, 4, I, MAXR>};
+  hipError_t e;
+  for (const void* f : xy)
+    if (ldsF <= kMaxDynLds && (e = set_lds(f, ldsF)) != hipSuccess) return e;
+  for (const void* f : inv)
+    if (ldsI <= kMaxDynLds && (e = set_lds(f, ldsI)) != hipSuccess) return e;
+  for (const void* f : upd)
+    if ((e = set_lds(f, ldsU)) != hipSuccess) return e;
+  if ((e = set_lds((const void*)k_x_fwd<T, MAXR>, ldsX)) != hipSuccess) return e;
+  if ((e = set_lds((const void*)k_x_inv<T, I, MAXR>, ldsX)) != hipSuccess) return e;
+  if ((e = set_lds((const void*)k_y<T, -1, MAXR>, ldsY)) != hipSuccess) return e;
+  return set_lds((const void*)k_y<T, 1, MAXR>, ldsY);
+}
+
+hipError_t prepare_kernels(bool f64, int ldsF, int ldsI, int ldsU, int ldsX, int ldsY) {
   hipError_t e;
   if (f64) {
-    if ((e = hipFuncSetAttribute((const void*)k_fwd_xy<double>, hipFuncAttributeMaxDynamicSharedMemorySize, ldsF)) != hipSuccess) return e;
-    if ((e = hipFuncSetAttribute((const void*)k_inv_xy<double, IncOf<double>::value>, hipFuncAttributeMaxDynamicSharedMemorySize, ldsI)) != hipSuccess) return e;
-    return set_upd_attr<double>(ldsU);
+    if ((e = prepare_t<double, 8>(ldsF, ldsI, ldsU, ldsX, ldsY)) != hipSuccess) return e;
+    return prepare_t<double, 16>(ldsF, ldsI, ldsU, ldsX, ldsY);
   }
-  if ((e = hipFuncSetAttribute((const void*)k_fwd_xy<float>, hipFuncAttributeMaxDynamicSharedMemorySize, ldsF)) != hipSuccess) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_inv_xy<float, IncOf<float>::value>, hipFuncAttributeMaxDynamicSharedMemorySize, ldsI)) != hipSuccess) return e;
-  return set_upd_attr<float>(ldsU);
+  if ((e = prepare_t<float, 8>(ldsF, ldsI, ldsU, ldsX, ldsY)) != hipSuccess) return e;
+  return prepare_t<float, 16>(ldsF, ldsI, ldsU, ldsX, ldsY);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -188,7 +223,17 @@ static hipError_t fwd_t(const DevPlan& p, const Batch& b, void* const* in9, void
   a.sbias = b.sbias;
   const int g = grid_for(b.nF, p.grid_cap[kPhaseFwd]);
   if (!g) return hipSuccess;
-  hipLaunchKernelGGL(k_fwd_xy<T>, dim3(g), dim3(kThreadsXY), p.ldsF, st, a, b.F0, b.nF, p.xcd);
+  if (p.ntxy == 512) {
+    if (p.maxr >= 16)
+      hipLaunchKernelGGL((k_fwd_xy<T, 512, 16>), dim3(g), dim3(512), p.ldsF, st, a, b.F0, b.nF, p.xcd);
+    else
+      hipLaunchKernelGGL((k_fwd_xy<T, 512, 8>), dim3(g), dim3(512), p.ldsF, st, a, b.F0, b.nF, p.xcd);
+  } else {
+    if (p.maxr >= 16)
+      hipLaunchKernelGGL((k_fwd_xy<T, 256, 16>), dim3(g), dim3(256), p.ldsF, st, a, b.F0, b.nF, p.xcd);
+    else
+      hipLaunchKernelGGL((k_fwd_xy<T, 256, 8>), dim3(g), dim3(256), p.ldsF, st, a, b.F0, b.nF, p.xcd);
+  }
   return hipGetLastError();
 }
 
@@ -196,10 +241,19 @@ hipError_t launch_fwd(const DevPlan& p, const Batch& b, void* const* in9, void* 
   return p.f64 ? fwd_t<double>(p, b, in9, spec, st) : fwd_t<float>(p, b, in9, spec, st);
 }
 
-template <typename T, int NT, int PB>
+template <typename T, int NT, int PB, int MAXR>
 static hipError_t upd_launch(const DevPlan& p, const Batch& b, const UpdArgs<T>& a, int g, hipStream_t st) {
-  hipLaunchKernelGGL((k_z_update<T, NT, PB, IncOf<T>::value>), dim3(g), dim3(NT), p.ldsU, st, a, b.U0, b.nU, p.xcd);
+  hipLaunchKernelGGL((k_z_update<T, NT, PB, IncOf<T>::value, MAXR>), dim3(g), dim3(NT), p.ldsU, st, a,
+                     b.U0, b.nU, p.xcd);
   return hipGetLastError();
+}
+
+template <typename T, int MAXR>
+static hipError_t upd_shape(const DevPlan& p, const Batch& b, const UpdArgs<T>& a, int g, hipStream_t st) {
+  if (p.PB == 4) return upd_launch<T, 512, 4, MAXR>(p, b, a, g, st);
+  if (p.ntu == 1024)
+    return p.PB == 16 ? upd_launch<T, 1024, 16, MAXR>(p, b, a, g, st) : upd_launch<T, 1024, 8, MAXR>(p, b, a, g, st);
+  return p.PB == 16 ? upd_launch<T, 512, 16, MAXR>(p, b, a, g, st) : upd_launch<T, 512, 8, MAXR>(p, b, a, g, st);
 }
 
 template <typename T>
@@ -214,14 +268,7 @@ static hipError_t upd_t(const DevPlan& p, const Batch& b, void* spec, hipStream_
   a.k.dt = p.dt;
   const int g = grid_for(b.nU, p.grid_cap[kPhaseUpd]);
   if (!g) return hipSuccess;
-  const bool big = p.NTU == 1024;
-  switch (p.PB) {
-    case 2: return big ? upd_launch<T, 1024, 2>(p, b, a, g, st) : upd_launch<T, 512, 2>(p, b, a, g, st);
-    case 4: return big ? upd_launch<T, 1024, 4>(p, b, a, g, st) : upd_launch<T, 512, 4>(p, b, a, g, st);
-    case 8: return big ? upd_launch<T, 1024, 8>(p, b, a, g, st) : upd_launch<T, 512, 8>(p, b, a, g, st);
-    case 16: return big ? upd_launch<T, 1024, 16>(p, b, a, g, st) : upd_launch<T, 512, 16>(p, b, a, g, st);
-    default: return hipErrorInvalidValue;
-  }
+  return p.maxr >= 16 ? upd_shape<T, 16>(p, b, a, g, st) : upd_shape<T, 8>(p, b, a, g, st);
 }
 
 hipError_t launch_upd(const DevPlan& p, const Batch& b, void* spec, hipStream_t st) {
@@ -239,12 +286,96 @@ static hipError_t inv_t(const DevPlan& p, const Batch& b, const void* spec, void
   for (int f = 0; f < 6; ++f) a.out[f] = reinterpret_cast<T*>(out6[f]);
   const int g = grid_for(b.nI, p.grid_cap[kPhaseInv]);
   if (!g) return hipSuccess;
-  hipLaunchKernelGGL((k_inv_xy<T, IncOf<T>::value>), dim3(g), dim3(kThreadsXY), p.ldsI, st, a, b.I0, b.nI, p.xcd);
+  constexpr bool I = IncOf<T>::value;
+  if (p.ntxy == 512) {
+    if (p.maxr >= 16)
+      hipLaunchKernelGGL((k_inv_xy<T, I, 512, 16>), dim3(g), dim3(512), p.ldsI, st, a, b.I0, b.nI, p.xcd);
+    else
+      hipLaunchKernelGGL((k_inv_xy<T, I, 512, 8>), dim3(g), dim3(512), p.ldsI, st, a, b.I0, b.nI, p.xcd);
+  } else {
+    if (p.maxr >= 16)
+      hipLaunchKernelGGL((k_inv_xy<T, I, 256, 16>), dim3(g), dim3(256), p.ldsI, st, a, b.I0, b.nI, p.xcd);
+    else
+      hipLaunchKernelGGL((k_inv_xy<T, I, 256, 8>), dim3(g), dim3(256), p.ldsI, st, a, b.I0, b.nI, p.xcd);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_inv(const DevPlan& p, const Batch& b, const void* spec, void* const* out6, hipStream_t st) {
   return p.f64 ? inv_t<double>(p, b, spec, out6, st) : inv_t<float>(p, b, spec, out6, st);
+}
+
+template <typename T>
+static SplitArgs<T> split_args(const DevPlan& p, void* spec) {
+  SplitArgs<T> a;
+  a.t = tables<T>(p);
+  a.items = nullptr;
+  for (int f = 0; f < 9; ++f) a.in[f] = nullptr;
+  for (int f = 0; f < 6; ++f) a.out[f] = nullptr;
+  a.spec = reinterpret_cast<cx<T>*>(spec);
+  a.slab = p.slab;
+  a.sbias = 0;
+  return a;
+}
+
+template <typename T>
+static hipError_t x_fwd_t(const DevPlan& p, void* const* in9, void* spec, hipStream_t st) {
+  SplitArgs<T> a = split_args<T>(p, spec);
+  a.items = p.itemsXF;
+  for (int f = 0; f < 9; ++f) a.in[f] = reinterpret_cast<const T*>(in9[f]);
+  const int g = grid_for(p.nXF, p.grid_cap[kPhaseFwd]);
+  if (!g) return hipSuccess;
+  if (p.maxr >= 16)
+    hipLaunchKernelGGL((k_x_fwd<T, 16>), dim3(g), dim3(kThreadsXY), p.ldsX, st, a, p.nXF, p.xcd);
+  else
+    hipLaunchKernelGGL((k_x_fwd<T, 8>), dim3(g), dim3(kThreadsXY), p.ldsX, st, a, p.nXF, p.xcd);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t y_t(const DevPlan& p, int dir, void* spec, hipStream_t st) {
+  SplitArgs<T> a = split_args<T>(p, spec);
+  a.items = dir < 0 ? p.itemsYF : p.itemsYI;
+  const int n = dir < 0 ? p.nYF : p.nYI;
+  const int g = grid_for(n, p.grid_cap[dir < 0 ? kPhaseFwd : kPhaseInv]);
+  if (!g) return hipSuccess;
+  if (dir < 0) {
+    if (p.maxr >= 16)
+      hipLaunchKernelGGL((k_y<T, -1, 16>), dim3(g), dim3(kThreadsXY), p.ldsY, st, a, n, p.xcd);
+    else
+      hipLaunchKernelGGL((k_y<T, -1, 8>), dim3(g), dim3(kThreadsXY), p.ldsY, st, a, n, p.xcd);
+  } else {
+    if (p.maxr >= 16)
+      hipLaunchKernelGGL((k_y<T, 1, 16>), dim3(g), dim3(kThreadsXY), p.ldsY, st, a, n, p.xcd);
+    else
+      hipLaunchKernelGGL((k_y<T, 1, 8>), dim3(g), dim3(kThreadsXY), p.ldsY, st, a, n, p.xcd);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t x_inv_t(const DevPlan& p, const void* spec, void* const* out6, hipStream_t st) {
+  SplitArgs<T> a = split_args<T>(p, const_cast<void*>(spec));
+  a.items = p.itemsXI;
+  for (int f = 0; f < 6; ++f) a.out[f] = reinterpret_cast<T*>(out6[f]);
+  const int g = grid_for(p.nXI, p.grid_cap[kPhaseInv]);
+  if (!g) return hipSuccess;
+  constexpr bool I = IncOf<T>::value;
+  if (p.maxr >= 16)
+    hipLaunchKernelGGL((k_x_inv<T, I, 16>), dim3(g), dim3(kThreadsXY), p.ldsX, st, a, p.nXI, p.xcd);
+  else
+    hipLaunchKernelGGL((k_x_inv<T, I, 8>), dim3(g), dim3(kThreadsXY), p.ldsX, st, a, p.nXI, p.xcd);
+  return hipGetLastError();
+}
+
+hipError_t launch_x_fwd(const DevPlan& p, void* const* in9, void* spec, hipStream_t st) {
+  return p.f64 ? x_fwd_t<double>(p, in9, spec, st) : x_fwd_t<float>(p, in9, spec, st);
+}
+hipError_t launch_y(const DevPlan& p, int dir, void* spec, hipStream_t st) {
+  return p.f64 ? y_t<double>(p, dir, spec, st) : y_t<float>(p, dir, spec, st);
+}
+hipError_t launch_x_inv(const DevPlan& p, const void* spec, void* const* out6, hipStream_t st) {
+  return p.f64 ? x_inv_t<double>(p, spec, out6, st) : x_inv_t<float>(p, spec, out6, st);
 }
 
 template <typename T>

@@ -25,9 +25,19 @@ struct DevPlan {
   const int32_t* itemsI;    // n[2] * 6
   const int32_t* itemsP;    // P[2]
   const int32_t* itemsN;    // n[2]
+  const int32_t* itemsXF;   // split passes: x forward, y forward, y inverse, x inverse
+  const int32_t* itemsYF;
+  const int32_t* itemsYI;
+  const int32_t* itemsXI;
+  int32_t nXF, nYF, nYI, nXI;
+  int32_t ldsX, ldsY;
+  int32_t split;
   int32_t nF, nU, nI, nP, nN;
   int32_t ldsF, ldsI, ldsU;  // dynamic LDS bytes per work-group
-  int32_t PB, NTU;           // pencils per z-update work-group, its thread count
+  int32_t PB;                // pencils per z-update work-group
+  int32_t ntu;               // threads per z-update work-group (512 or 1024)
+  int32_t ntxy;              // threads per x/y work-group (256 or 512)
+  int32_t maxr;              // largest codelet of the FFT schedules (8 or 16)
   int32_t xcd;               // 1: consecutive items on the same XCD (L2 sharing)
   int64_t slab;              // complex elements of one spectral field slab
   double c, dt;
@@ -39,11 +49,15 @@ hipError_t launch_sum(const DevPlan& p, void* const* J, hipStream_t st);
 hipError_t launch_fwd(const DevPlan& p, const Batch& b, void* const* in9, void* spec, hipStream_t st);
 hipError_t launch_upd(const DevPlan& p, const Batch& b, void* spec, hipStream_t st);
 hipError_t launch_inv(const DevPlan& p, const Batch& b, const void* spec, void* const* out6, hipStream_t st);
+// split x/y passes (whole plan, no batching)
+hipError_t launch_x_fwd(const DevPlan& p, void* const* in9, void* spec, hipStream_t st);
+hipError_t launch_y(const DevPlan& p, int dir, void* spec, hipStream_t st);
+hipError_t launch_x_inv(const DevPlan& p, const void* spec, void* const* out6, hipStream_t st);
 hipError_t launch_scatter(const DevPlan& p, const void* const* glob, void* const* pad, hipStream_t st);
 hipError_t launch_gather(const DevPlan& p, const void* const* pad, void* const* glob, hipStream_t st);
 hipError_t launch_modk(const KEntry* entries, int nent, int maxN, int order_p, double* kmod,
                        hipStream_t st);
-hipError_t prepare_kernels(bool f64, int ldsF, int ldsI, int ldsU);
+hipError_t prepare_kernels(bool f64, int ldsF, int ldsI, int ldsU, int ldsX, int ldsY);
 
 
 }  // namespace psatd

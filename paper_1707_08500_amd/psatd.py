@@ -24,7 +24,8 @@ PRECISIONS = {"f64": F64, "f32": F32_VALU, "f32_valu": F32_VALU,
 JMODES = {"replicated": J_REPLICATED, "deposited": J_DEPOSITED}
 PHASES = ("exchange_J", "fft_xy_fwd", "z_update", "fft_xy_inv", "exchange_EB")
 TUNING = {"z_pencils": 0, "xcd_remap": 1, "grid_fwd": 2, "grid_upd": 3, "grid_inv": 4,
-          "grid_exch": 5, "batch_boxes": 6}
+          "grid_exch": 5, "batch_boxes": 6, "max_radix": 7, "xy_threads": 8, "z_threads": 9,
+          "split_xy": 10}
 NPHASES = len(PHASES)
 
 STATUS = {0: "PSATD_OK", 1: "PSATD_E_INVALID", 2: "PSATD_E_NOMEM", 3: "PSATD_E_HIP",
@@ -33,7 +34,7 @@ STATUS = {0: "PSATD_OK", 1: "PSATD_E_INVALID", 2: "PSATD_E_NOMEM", 3: "PSATD_E_H
 SYMBOLS = ("psatd_plan", "psatd_validate", "psatd_field_elems", "psatd_field_layout",
            "psatd_workspace_bytes", "psatd_set_workspace", "psatd_step", "psatd_run",
            "psatd_run_profiled", "psatd_scatter", "psatd_gather", "psatd_modified_k",
-           "psatd_set_tuning", "psatd_get_tuning", "psatd_set_stream", "psatd_sync", "psatd_destroy", "psatd_status_string",
+           "psatd_set_tuning", "psatd_get_tuning", "psatd_autotune", "psatd_set_stream", "psatd_sync", "psatd_destroy", "psatd_status_string",
            "psatd_last_error", "psatd_version")
 
 
@@ -68,6 +69,7 @@ def _load():
         "psatd_modified_k": ([P, i32, i32, DP, i64], i32),
         "psatd_set_tuning": ([P, i32, i32], i32),
         "psatd_get_tuning": ([P, i32, I32P], i32),
+        "psatd_autotune": ([P, VPP, VPP, VPP, i32, ctypes.c_char_p, DP], i32),
         "psatd_set_stream": ([P, P], i32),
         "psatd_sync": ([P], i32),
         "psatd_destroy": ([P], None),
@@ -210,6 +212,15 @@ class Plan:
             _check(LIB.psatd_get_tuning(self._h, key, ctypes.byref(v)), self._h)
             out[k] = v.value
         return out
+
+    def autotune(self, E, B, J, steps_per_trial=3, cache_path=None):
+        """Times launch-shape candidates (advancing E, B) and applies the fastest;
+        returns the tuned step time in ms (0.0 on a cache hit)."""
+        out = ctypes.c_double(0.0)
+        cp = cache_path.encode() if cache_path else None
+        _check(LIB.psatd_autotune(self._h, _ptrs(E), _ptrs(B), _ptrs(J), int(steps_per_trial), cp,
+                                  ctypes.byref(out)), self._h)
+        return out.value
 
     def set_stream(self, stream):
         _check(LIB.psatd_set_stream(self._h, ctypes.c_void_p(stream)), self._h)

@@ -73,9 +73,13 @@ def test_scatter_gather_exact(precision):
 
 # ---------------------------------------------------- step vs the oracle
 def run_both(N, lo, n, g, p, dt, c, precision, jmode, fields, steps, d=(1.0, 1.0, 1.0),
-             J_boxes=None):
+             J_boxes=None, tuning=None):
     E, B, J = fields
     case = GpuCase(N, lo, n, g, p, dt, c, precision, jmode, E, B, J, d=d)
+    if tuning:
+        case.plan.set_tuning(**tuning)
+        got = case.plan.tuning()
+        assert all(got[k] == v for k, v in tuning.items()), got
     if J_boxes is not None:  # deposited partial currents per copy
         import torch
         for a in range(3):
@@ -374,7 +378,7 @@ def test_config4_uneven_full_size_one_step_sampled():
 
 
 # ----------------- configuration 5 cutout: 176^3 local boxes, p = 100
-@pytest.mark.parametrize("precision,tol", [("f32", TOL32)])
+@pytest.mark.parametrize("precision,tol", [("f32", TOL32), ("f64", TOL64)])
 def test_config5_cutout(precision, tol):
     """Same local shape and order as configuration 5 (128^3 + 24 guards =
     176^3, p = 100) on a 256^3 grid of 2x2x2 boxes, laser-like pulse plus
@@ -389,3 +393,104 @@ def test_config5_cutout(precision, tol):
         E, B, J = (x.astype(np.float32).astype(np.float64) for x in (E, B, J))
     case, eE, eB, _ = run_both(N, lo, n, g, 100, 0.5, 1.0, precision, "replicated", (E, B, J), 1)
     check(case, eE, eB, precision, tol)
+
+
+# ------------------------------------------------ launch shapes, autotuner
+def test_launch_shapes_do_not_change_results(tmp_path):
+    """Every tuning knob changes only the schedule: the FP64 result of every
+    setting matches the default to rounding, and an invalid setting is
+    rejected without changing the plan."""
+    from paper_1707_08500_amd import psatd
+    say("tuning knobs")
+    N = (48, 48, 48)
+    lo, n, g = synth.uniform_decomposition(N, (2, 2, 2), 8)
+    E, B, J = random_fields(N, 12, p=16)
+    case = GpuCase(N, lo, n, g, 16, 0.5, 1.0, "f64", "replicated", E, B, J)
+    ref = None
+    settings = [dict(), dict(max_radix=8), dict(xy_threads=512), dict(z_threads=1024),
+                dict(z_pencils=8), dict(xcd_remap=0), dict(batch_boxes=3),
+                dict(grid_fwd=100, grid_upd=64, grid_inv=96, grid_exch=50),
+                dict(max_radix=8, xy_threads=512, z_threads=1024, batch_boxes=2)]
+    for st in settings:
+        for glob, pad in ((E, case.E), (B, case.B), (J, case.J)):
+            import torch
+            case.plan.scatter([torch.from_numpy(np.ascontiguousarray(glob[a])).cuda().reshape(-1)
+                               for a in range(3)], pad)
+        case.plan.set_tuning(**st)
+        case.plan.run(case.E, case.B, case.J, 2)
+        case.plan.sync()
+        got = case.gathered(case.E)
+        if ref is None:
+            ref = got
+        else:
+            assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max(), st
+        case.plan.set_tuning(max_radix=16, xy_threads=256, z_threads=512, z_pencils=8,
+                             xcd_remap=1, batch_boxes=0, grid_fwd=0, grid_upd=0, grid_inv=0,
+                             grid_exch=0)
+    before = case.plan.tuning()
+    with pytest.raises(psatd.PsatdError):
+        case.plan.set_tuning(z_pencils=3)
+    with pytest.raises(psatd.PsatdError):
+        case.plan.set_tuning(xy_threads=300)
+    assert case.plan.tuning() == before
+    # autotuner: times, applies, caches; a second call hits the cache
+    cache = str(tmp_path / "psatd_tune.txt")
+    t1 = case.plan.autotune(case.E, case.B, case.J, steps_per_trial=1, cache_path=cache)
+    tuned = case.plan.tuning()
+    assert t1 > 0.0
+    case.plan.set_tuning(max_radix=16, xy_threads=256, z_threads=512)
+    t2 = case.plan.autotune(case.E, case.B, case.J, steps_per_trial=1, cache_path=cache)
+    assert t2 == 0.0 and case.plan.tuning() == tuned
+    say(f"  autotuned {tuned} ({t1:.3f} ms/step)")
+
+
+# ------------------------------------ split x/y passes and PSATD-global
+@pytest.mark.parametrize("precision,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_split_xy_passes(precision, tol):
+    """The x-row / y-column passes (the form used when a plane exceeds the
+    LDS), forced on small uneven boxes, against the oracle."""
+    say(f"split x/y uneven {precision}")
+    N, lo, n, g = uneven_small()
+    fields = random_fields(N, 13, p=4)
+    case, eE, eB, _ = run_both(N, lo, n, g, 4, 0.3, 1.0, precision, "replicated", fields, 2,
+                               tuning=dict(split_xy=1))
+    check(case, eE, eB, precision, tol)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_split_xy_uniform_deep_z(precision, tol):
+    """Split passes with a tall z axis (z tiles of 4 pencils) on 2x2x1 boxes."""
+    say(f"split x/y 64x48x148 {precision}")
+    N = (64, 48, 148)
+    lo, n, g = synth.uniform_decomposition(N, (2, 2, 1), 6)
+    fields = random_fields(N, 15, p=16)
+    case, eE, eB, _ = run_both(N, lo, n, g, 16, 0.5, 1.0, precision, "replicated", fields, 2,
+                               tuning=dict(split_xy=1))
+    check(case, eE, eB, precision, tol)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_psatd_global_on_gpu(precision, tol):
+    """PSATD-global (Sec. 3.2, the scheme of Fig. 2b): one box covering the
+    whole periodic grid without guards, i.e. one global FFT per step; its
+    256x192 planes exceed the LDS, so the split passes run."""
+    say(f"PSATD-global 256x192x64 {precision}")
+    N = (256, 192, 64)
+    d = (1.0, 1.0, 1.0)
+    E, B, J = random_fields(N, 14, p=16)
+    case = GpuCase(N, [[0, 0, 0]], [list(N)], [[0, 0, 0]], 16, 0.5, 1.0, precision, "replicated",
+                   E, B, J)
+    assert case.plan.tuning()["split_xy"] == 1
+    case.plan.run(case.E, case.B, case.J, 3)
+    case.plan.sync()
+    gE, gB = case.gathered(case.E), case.gathered(case.B)
+    oE, oB = O.run_global(E, B, J, d, 16, 1.0, 0.5, 3)
+    num = float(np.sum((gE - oE) ** 2) + np.sum((gB - oB) ** 2))
+    den = float(np.sum(oE ** 2) + np.sum(oB ** 2))
+    en = float(np.sqrt(num / den))
+    say(f"  energy-norm rel-L2 vs the global oracle {en:.3e}")
+    assert en <= tol
+    if precision == "f64":
+        for a in range(3):
+            assert O.rel_l2(gE[a], oE[a]) <= tol
+            assert O.rel_l2(gB[a], oB[a]) <= tol
