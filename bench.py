@@ -15,6 +15,9 @@ orthogonal to the grid wave vector).
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -25,6 +28,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "PSATD cell-updates/s at 1 GPU (FP32/MFMA vs FP64 plain) at <=1e-5 rel L2; % HBM BW"
 HBM_PEAK_GBS = 8000.0
+CSRC = os.path.join(ROOT, "paper_1707_08500_amd", "csrc")
+PHASE_KERNEL = {"fft_xy_fwd": "k_fwd_xy", "z_update": "k_z_update", "fft_xy_inv": "k_inv_xy",
+                "exchange_EB": "k_fill", "exchange_J": "k_fill"}
+COPY_BYTES = 1 << 30  # the calibration copy: 2^28 floats read and written
 
 WORKLOADS = {
     # name: grid, boxes per axis, guard, order p, dt
@@ -94,6 +101,107 @@ def timed_run(plan, E, B, J, glob_init, steps, warmup):
     return time.perf_counter() - t0
 
 
+def source_digest():
+    """sha256 over the kernel sources: HBM counters taken on other sources are stale."""
+    h = hashlib.sha256()
+    for path in sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.hpp"))
+                       + glob.glob(os.path.join(CSRC, "*.h"))):
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_path(workload):
+    return os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.txt")
+
+
+def _pmc_rows(path, counter):
+    """Per-dispatch values of one counter from a rocprofv3 counter_collection.csv."""
+    rows = []
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def summarize_pmc(fetch_csv, write_csv, workload, command):
+    """HBM bytes per dispatch of every psatd kernel from a FETCH_SIZE run and a
+    WRITE_SIZE run (KiB per dispatch), each scaled by the factor that makes the
+    1 GiB calibration copy read and write exactly 1 GiB."""
+    out = {}
+    factors = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = _pmc_rows(path, counter)
+        # the calibration dispatches are the only ones outside the library that
+        # move more than 256 MiB: the 1 GiB fill (writes) and the 1 GiB copies
+        copies = [v for name, v in rows if "psatd" not in name and v > 0.25 * COPY_BYTES / 1024]
+        if not copies:
+            raise SystemExit(f"no 1 GiB calibration dispatch among the {counter} dispatches")
+        factors[counter] = (COPY_BYTES / 1024) / (sum(copies) / len(copies))
+        factors[counter + "_n"] = len(copies)
+        per = {}
+        for name, v in rows:
+            short = name.split("(")[0].replace("void ", "").strip()
+            base = short.split("<")[0].split("::")[-1]
+            if base in PHASE_KERNEL.values() or base.startswith("k_"):
+                per.setdefault(short, []).append(v)
+        for short, vals in per.items():
+            out.setdefault(short, {})[counter] = (sum(vals) / len(vals), len(vals))
+    lines = [f"# HBM traffic per dispatch, workload {workload} (rocprofv3 --pmc, two passes)",
+             f"# command: {command}",
+             f"source_digest: {source_digest()}",
+             f"copy_factor FETCH_SIZE: {factors['FETCH_SIZE']:.6f} "
+             f"(from {factors['FETCH_SIZE_n']} calibration dispatches)",
+             f"copy_factor WRITE_SIZE: {factors['WRITE_SIZE']:.6f} "
+             f"(from {factors['WRITE_SIZE_n']} calibration dispatches)",
+             "# kernel | dispatches | FETCH_SIZE KiB (raw) | WRITE_SIZE KiB (raw) | HBM bytes (scaled)"]
+    for short, d in sorted(out.items()):
+        fk, n = d.get("FETCH_SIZE", (0.0, 0))
+        wk, _ = d.get("WRITE_SIZE", (0.0, 0))
+        b = 1024 * (fk * factors["FETCH_SIZE"] + wk * factors["WRITE_SIZE"])
+        lines.append(f"kernel {short} | {n} | {fk:.1f} | {wk:.1f} | {b:.0f}")
+    return "\n".join(lines) + "\n"
+
+
+def summarize_ktrace(stats_csv, bench_line, workload, command):
+    """Per-kernel launch statistics from rocprofv3 --kernel-trace --stats, next to
+    the per-phase times the same run measured with HIP events."""
+    lines = [f"# rocprofv3 kernel statistics, workload {workload}",
+             f"# command: {command}",
+             f"source_digest: {source_digest()}",
+             "# kernel | calls | average us | total ms | % of GPU time"]
+    for r in csv.DictReader(open(stats_csv)):
+        short = r["Name"].split("(")[0].replace("void ", "").strip()
+        lines.append(f"{short} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | {r['Percentage']}")
+    if bench_line:
+        d = json.loads(bench_line)
+        lines.append("# the same run's bench line (FP32 path), per-phase ms from HIP events:")
+        lines.append("phases_ms " + " ".join(f"{k}={v:.3f}" for k, v in d["phases_ms"].items()))
+        lines.append(f"ms_per_step {d['ms_per_step']:.3f}")
+    return "\n".join(lines) + "\n"
+
+
+def read_traffic(workload, kernel):
+    """Scaled HBM bytes per dispatch of `kernel` from the committed summary, or
+    None when there is none or it was taken on other kernel sources."""
+    path = traffic_path(workload)
+    if not os.path.exists(path):
+        return None
+    digest, found = None, None
+    for line in open(path):
+        if line.startswith("source_digest:"):
+            digest = line.split(":", 1)[1].strip()
+        elif line.startswith("kernel "):
+            fields = [f.strip() for f in line[len("kernel "):].split("|")]
+            if fields[0].split("<")[0].split("::")[-1] == kernel:
+                found = float(fields[4]) if found is None else max(found, float(fields[4]))
+    if digest != source_digest():
+        return None
+    return found
+
+
 def cpu_baseline(N, d, lo, n, g, p, dt, E, B, J, budget_s=15.0):
     """The oracle as it stands, on a bounded sample of subdomains of the same
     workload (one local step each: local FFTs, update, inverse FFTs)."""
@@ -127,10 +235,31 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=5)
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time launch-shape candidates first (the defaults are the measured best for cfg2)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM-traffic summary from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--pmc-command", default="", help="the profiled command, recorded in the summary")
+    ap.add_argument("--summarize-ktrace", nargs=2, metavar=("KERNEL_STATS_CSV", "BENCH_LOG"),
+                    help="print the kernel-statistics summary of a rocprofv3 --stats run and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        text = summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload,
+                             args.pmc_command)
+        with open(traffic_path(args.workload), "w") as f:
+            f.write(text)
+        print(text, end="")
+        return
+    if args.summarize_ktrace:
+        bench_line = ""
+        for line in open(args.summarize_ktrace[1]):
+            if line.startswith("{"):
+                bench_line = line
+        print(summarize_ktrace(args.summarize_ktrace[0], bench_line, args.workload, args.pmc_command),
+              end="")
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               f"(the single-GPU kernel is the per-GPU share of a sharded run)", file=sys.stderr)
@@ -141,7 +270,7 @@ def main():
     from paper_1707_08500_amd import psatd, synth
 
     if args.copy_calibration:
-        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
@@ -165,7 +294,7 @@ def main():
         glob = [[torch.from_numpy(np.ascontiguousarray(F[a])).to("cuda", dtype).reshape(-1)
                  for a in range(3)] for F in (E0, B0, J0)]
         E, B, J = plan.empty_fields(), plan.empty_fields(), plan.empty_fields()
-        if not args.no_autotune:
+        if args.autotune:
             for F, pad in zip(glob, (E, B, J)):
                 plan.scatter(F, pad)
             tuned_ms = plan.autotune(E, B, J, steps_per_trial=3)
@@ -225,7 +354,9 @@ def main():
             "per_pass_algorithmic": (step_algo / (sum(phases.values()) * 1e-3)) / 1e9 / HBM_PEAK_GBS,
         },
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": read_traffic(args.workload, PHASE_KERNEL[dom]),
+                     "algorithmic_bytes": r32["algo_bytes"][dom]},
     }
     if "f64" in results:
         r64 = results["f64"]

@@ -417,7 +417,12 @@ inline psatd_status build_host(HostTables& h, std::string& err, const int64_t gr
   prefix(h.itemsYI, [](const BoxD& b) { return (int64_t)b.n[2] * 6 * ((b.H + kCB - 1) / kCB); });
   prefix(h.itemsXI, [](const BoxD& b) { return (int64_t)b.n[2] * 6 * ((b.n[1] + kRB - 1) / kRB); });
   set_batches(h, 0);
+  // launch-shape defaults measured on the 96^3 local boxes: FP32 runs 256-thread
+  // x/y groups with radix-16 stages and 1024-thread z tiles; FP64 (twice the
+  // registers per value) runs 512-thread x/y groups with stages of radix <= 8
   h.ntu = f64 ? 512 : 1024;
+  h.ntxy = f64 ? 512 : 256;
+  if (f64 && !set_max_radix(h, 8)) return bad(PSATD_E_UNSUPPORTED, "no radix-8 schedule");
   return PSATD_OK;
 }
 
