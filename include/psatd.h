@@ -63,8 +63,12 @@ typedef enum {
 typedef enum {
   PSATD_F64 = 0,        /* FP64 state, FP64 FFT, FP64 update */
   PSATD_F32_VALU = 1,   /* FP32 state and FFT (vector ALU), FP64 coefficients and update */
-  PSATD_F32_BF16X3 = 2, /* FP32 state, DFT stages as split-BF16 3-product MFMA GEMMs */
-  PSATD_F32_BF16X6 = 3  /* FP32 state, DFT stages as split-BF16 6-product MFMA GEMMs */
+  /* FP32 state; the first (radix-16) stage of every transform whose length is a
+     multiple of 16 is a complex 16x16 DFT-GEMM on the matrix cores with the FP32
+     operands split into BF16 terms and FP32 accumulation; the other stages as
+     F32_VALU; FP64 coefficients and update. */
+  PSATD_F32_BF16X3 = 2, /* 2 terms per operand, 3 products (hi*hi + hi*lo + lo*hi) */
+  PSATD_F32_BF16X6 = 3  /* 3 terms per operand, the 6 products of term order <= 2 */
 } psatd_precision;
 
 typedef enum {
@@ -98,7 +102,11 @@ typedef enum {
   PSATD_TUNE_Z_THREADS = 9,   /* threads per work-group of the z-update: 512 or 1024 */
   PSATD_TUNE_SPLIT_XY = 10,   /* 1: x rows and y columns in separate passes through the workspace
                                  (automatic when a padded plane exceeds the LDS; needs no batching) */
-  PSATD_NTUNE = 11
+  PSATD_TUNE_FUSE_EB = 11,    /* 1: the inverse pass writes each new E, B value into every guard copy
+                                 of its cell, so the E,B exchange needs no pass of its own (same bytes
+                                 as the copy pass); 0 (default, faster on 96^3 boxes): a separate copy
+                                 pass.  Batching (PSATD_TUNE_BATCH_BOXES) turns it off. */
+  PSATD_NTUNE = 12
 } psatd_tune_key;
 
 /*

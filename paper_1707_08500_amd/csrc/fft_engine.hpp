@@ -308,6 +308,20 @@ PSATD_HD void fft_dit(cx<T>* buf, int M, int ms, int es, const FftPlanD* pl, con
   }
 }
 
+// FFT engine of the kernel bodies: every stage as a VALU radix stage.
+struct FftValu {
+  template <int DIR, int MAXR, typename T, class Bar>
+  PSATD_HD void dif(cx<T>* buf, int M, int ms, int es, const FftPlanD* pl, const cx<T>* tw, int tid,
+                    int nt, Bar bar) const {
+    fft_dif<DIR, MAXR>(buf, M, ms, es, pl, tw, tid, nt, bar);
+  }
+  template <int DIR, int MAXR, typename T, class Bar>
+  PSATD_HD void dit(cx<T>* buf, int M, int ms, int es, const FftPlanD* pl, const cx<T>* tw, int tid,
+                    int nt, Bar bar) const {
+    fft_dit<DIR, MAXR>(buf, M, ms, es, pl, tw, tid, nt, bar);
+  }
+};
+
 // ------------------------------------------- real <-> half-spectrum helpers
 // A real row a[0..N) (N = 2 Nh) is packed as z[n] = a[2n] + i a[2n+1].  With
 // Z = FFT_Nh(z) in natural order in row[0..Nh), r2c_post turns the pair

@@ -36,6 +36,9 @@ struct HostTables {
   std::vector<int32_t> itemsF, itemsU, itemsI, itemsP, itemsN;
   std::vector<int32_t> itemsXF, itemsYF, itemsYI, itemsXI;  // split x/y passes
   bool split = false;  // x/y pass split into x rows and y columns (large planes)
+  std::vector<PushBlk> push;      // fused E,B exchange: guard pieces per source box
+  std::vector<int32_t> push_off;  // nsub + 1
+  bool fuse_eb = false;           // E,B guards written by the inverse pass
   int ldsX = 0, ldsY = 0;
   std::vector<Batch> batches;
   int64_t batch_slab = 0;     // complex elements of one spectral field slab of the largest batch
@@ -44,6 +47,7 @@ struct HostTables {
   int64_t slab = 0;
   int ldsF = 0, ldsI = 0, ldsU = 0, PB = 0;
   int maxr = 16;      // largest radix used by the FFT schedules (8 or 16; 11 always)
+  int spl = 0;        // BF16 terms of the matrix-core first stage (0: VALU form)
   int ntxy = 512;     // threads per work-group of the x/y passes
   int ntu = 512;      // threads per work-group of the z-update (1024 for FP32 by default)
 };
@@ -98,6 +102,19 @@ inline bool factorize(int N, std::vector<int>& out, int maxr = 16) {
   return false;
 }
 
+// Schedule of a transform: with a matrix-core first stage (spl > 0) every
+// length divisible by 16 starts with radix 16, the rest as factorize().
+inline bool schedule(int N, std::vector<int>& out, int maxr, int spl) {
+  if (spl > 0 && N % 16 == 0) {
+    std::vector<int> rest;
+    if (!factorize(N / 16, rest, maxr) || rest.size() + 1 > (size_t)kMaxStages) return false;
+    out.assign(1, 16);
+    out.insert(out.end(), rest.begin(), rest.end());
+    return true;
+  }
+  return factorize(N, out, maxr);
+}
+
 // Fills the stage fields of a plan of length pl.N from a radix list.
 inline void set_stages(FftPlanD& pl, const std::vector<int>& rad) {
   const int N = pl.N;
@@ -130,7 +147,7 @@ inline int add_plan(HostTables& h, int N) {
   for (size_t i = 0; i < h.plans.size(); ++i)
     if (h.plans[i].N == N) return (int)i;
   std::vector<int> rad;
-  if (!factorize(N, rad, h.maxr)) return -1;
+  if (!schedule(N, rad, h.maxr, h.spl)) return -1;
   FftPlanD pl{};
   pl.N = N;
   set_stages(pl, rad);
@@ -223,7 +240,7 @@ inline bool set_max_radix(HostTables& h, int maxr) {
   std::vector<FftPlanD> plans = h.plans;
   for (FftPlanD& pl : plans) {
     std::vector<int> rad;
-    if (!factorize(pl.N, rad, maxr)) return false;
+    if (!schedule(pl.N, rad, maxr, h.spl)) return false;
     set_stages(pl, rad);
   }
   h.plans = plans;
@@ -235,6 +252,60 @@ inline int max_padded_z(const HostTables& h) {
   int m = 0;
   for (const BoxD& b : h.box) m = std::max(m, b.P[2]);
   return m;
+}
+
+// Runs of padded positions q of box d (global coordinate lo_d - g_d + q mod N)
+// that fall on the interior [lo_s, lo_s + n_s) of box s, as (i0, q0, len) with
+// i the interior index of s; consecutive q with consecutive i form one run.
+struct Run {
+  int32_t i0, q0, len;
+};
+inline void axis_runs(int64_t lo_s, int64_t n_s, int64_t lo_d, int64_t g_d, int64_t P_d, int64_t N,
+                      std::vector<Run>& out) {
+  out.clear();
+  for (int64_t q = 0; q < P_d; ++q) {
+    const int64_t G = ((lo_d - g_d + q) % N + N) % N;
+    const int64_t i = ((G - lo_s) % N + N) % N;
+    if (i >= n_s) continue;
+    if (!out.empty()) {
+      Run& r = out.back();
+      if (r.q0 + r.len == q && r.i0 + r.len == i) {
+        ++r.len;
+        continue;
+      }
+    }
+    out.push_back({(int32_t)i, (int32_t)q, 1});
+  }
+}
+
+// Guard pieces for the fused E,B exchange (every guard cell of every box in
+// exactly one piece; the interior of each box itself excluded).
+inline void build_push(HostTables& h) {
+  const int nsub = h.nsub;
+  h.push.clear();
+  h.push_off.assign(nsub + 1, 0);
+  std::vector<Run> rz, ry, rx;
+  for (int s = 0; s < nsub; ++s) {
+    const BoxD& a = h.box[s];
+    for (int d = 0; d < nsub; ++d) {
+      const BoxD& b = h.box[d];
+      axis_runs(a.lo[2], a.n[2], b.lo[2], b.g[2], b.P[2], h.N[2], rz);
+      if (rz.empty()) continue;
+      axis_runs(a.lo[1], a.n[1], b.lo[1], b.g[1], b.P[1], h.N[1], ry);
+      if (ry.empty()) continue;
+      axis_runs(a.lo[0], a.n[0], b.lo[0], b.g[0], b.P[0], h.N[0], rx);
+      if (rx.empty()) continue;
+      for (const Run& z : rz)
+        for (const Run& y : ry)
+          for (const Run& x : rx) {
+            const bool own = d == s && z.q0 == b.g[2] && y.q0 == b.g[1] && x.q0 == b.g[0] &&
+                             z.i0 == 0 && y.i0 == 0 && x.i0 == 0;
+            if (own) continue;  // the interior itself
+            h.push.push_back({d, z.i0, z.len, z.q0, y.i0, y.len, y.q0, x.i0, x.len, x.q0});
+          }
+    }
+    h.push_off[s + 1] = (int32_t)h.push.size();
+  }
 }
 
 // Does the circular interval [a, a+len) (len < N) meet [lo, lo+n) on Z_N?
@@ -266,8 +337,6 @@ inline psatd_status build_host(HostTables& h, std::string& err, const int64_t gr
   if (!(dt != 0.0) || !std::isfinite(dt)) return bad(PSATD_E_INVALID, "dt must be finite and nonzero");
   if (!(c > 0.0) || !std::isfinite(c)) return bad(PSATD_E_INVALID, "c must be finite and > 0");
   if (precision < PSATD_F64 || precision > PSATD_F32_BF16X6) return bad(PSATD_E_INVALID, "unknown precision");
-  if (precision == PSATD_F32_BF16X3 || precision == PSATD_F32_BF16X6)
-    return bad(PSATD_E_UNSUPPORTED, "split-BF16 MFMA DFT stages are not built in this library version");
   if (jmode != PSATD_J_REPLICATED && jmode != PSATD_J_DEPOSITED) return bad(PSATD_E_INVALID, "unknown jmode");
 
   for (int u = 0; u < 3; ++u) {
@@ -280,6 +349,7 @@ inline psatd_status build_host(HostTables& h, std::string& err, const int64_t gr
   h.c = c;
   h.prec = precision;
   h.jmode = jmode;
+  h.spl = precision == PSATD_F32_BF16X3 ? 2 : (precision == PSATD_F32_BF16X6 ? 3 : 0);
 
   // boxes inside the grid, guards >= 0
   for (int s = 0; s < nsub; ++s)
@@ -416,11 +486,12 @@ inline psatd_status build_host(HostTables& h, std::string& err, const int64_t gr
   prefix(h.itemsYF, [](const BoxD& b) { return (int64_t)b.P[2] * 9 * ((b.H + kCB - 1) / kCB); });
   prefix(h.itemsYI, [](const BoxD& b) { return (int64_t)b.n[2] * 6 * ((b.H + kCB - 1) / kCB); });
   prefix(h.itemsXI, [](const BoxD& b) { return (int64_t)b.n[2] * 6 * ((b.n[1] + kRB - 1) / kRB); });
+  build_push(h);
   set_batches(h, 0);
   // launch-shape defaults measured on the 96^3 local boxes: FP32 runs 256-thread
   // x/y groups with radix-16 stages and 1024-thread z tiles; FP64 (twice the
   // registers per value) runs 512-thread x/y groups with stages of radix <= 8
-  h.ntu = f64 ? 512 : 1024;
+  h.ntu = (f64 || h.spl) ? 512 : 1024;  // the matrix-core z tiles spill at 1024 threads
   h.ntxy = f64 ? 512 : 256;
   if (f64 && !set_max_radix(h, 8)) return bad(PSATD_E_UNSUPPORTED, "no radix-8 schedule");
   return PSATD_OK;

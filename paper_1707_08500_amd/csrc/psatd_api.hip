@@ -42,7 +42,7 @@ struct psatd_plan_s {
   int device = 0;
   void* blob = nullptr;  // device tables
   int32_t* d_itemsU = nullptr;  // z-update work list (depends on the z tile)
-  int32_t tune[PSATD_NTUNE] = {0, 1, 0, 0, 0, 0, 0, 16, 256, 512, 0};
+  int32_t tune[PSATD_NTUNE] = {0, 1, 0, 0, 0, 0, 0, 16, 256, 512, 0, 1};
   void* ws = nullptr;
   int64_t ws_bytes = 0;
   bool ws_owned = false;
@@ -159,7 +159,7 @@ psatd_status enqueue_step(psatd_plan_t p, void* const E[3], void* const B[3], vo
     PSATD_MARK(kPhaseInv, false);
   }
   PSATD_MARK(kPhaseExchEB, true);
-  HIPCHK(p, launch_fill(d, eb, 6, st));
+  if (!d.fuse) HIPCHK(p, launch_fill(d, eb, 6, st));  // fused: written by the inverse pass
   PSATD_MARK(kPhaseExchEB, false);
 #undef PSATD_MARK
   return PSATD_OK;
@@ -261,6 +261,8 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   const size_t o_iYF = reserve(h.itemsYF.size() * 4);
   const size_t o_iYI = reserve(h.itemsYI.size() * 4);
   const size_t o_iXI = reserve(h.itemsXI.size() * 4);
+  const size_t o_push = reserve(std::max<size_t>(h.push.size(), 1) * sizeof(PushBlk));
+  const size_t o_pof = reserve(h.push_off.size() * 4);
   std::vector<unsigned char> hb(total, 0);
   auto put = [&](size_t off, const void* src, size_t bytes) {
     if (bytes) std::memcpy(hb.data() + off, src, bytes);
@@ -289,6 +291,8 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   put(o_iYF, h.itemsYF.data(), h.itemsYF.size() * 4);
   put(o_iYI, h.itemsYI.data(), h.itemsYI.size() * 4);
   put(o_iXI, h.itemsXI.data(), h.itemsXI.size() * 4);
+  put(o_push, h.push.data(), h.push.size() * sizeof(PushBlk));
+  put(o_pof, h.push_off.data(), h.push_off.size() * 4);
   if ((e = hipMalloc(&p->blob, total)) != hipSuccess) return hipfail(e, "hipMalloc(tables)");
   if ((e = hipMemcpy(p->blob, hb.data(), total, hipMemcpyHostToDevice)) != hipSuccess)
     return hipfail(e, "hipMemcpy(tables)");
@@ -306,7 +310,7 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
                        reinterpret_cast<double*>(B + o_kmod), p->cap_stream)) != hipSuccess)
     return hipfail(e, "modified-wavenumber kernel");
   if ((e = hipStreamSynchronize(p->cap_stream)) != hipSuccess) return hipfail(e, "modified-wavenumber kernel");
-  if ((e = prepare_kernels(f64, h.ldsF, h.ldsI, h.ldsU, h.ldsX, h.ldsY)) != hipSuccess)
+  if ((e = prepare_kernels(f64, h.spl, h.ldsF, h.ldsI, h.ldsU, h.ldsX, h.ldsY)) != hipSuccess)
     return hipfail(e, "hipFuncSetAttribute");
 
   DevPlan& d = p->dp;
@@ -342,6 +346,11 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   d.ldsX = h.ldsX;
   d.ldsY = h.ldsY;
   d.split = h.split ? 1 : 0;
+  d.push = reinterpret_cast<const PushBlk*>(B + o_push);
+  d.push_off = reinterpret_cast<const int32_t*>(B + o_pof);
+  d.fuse = (h.fuse_eb && h.batches.size() == 1) ? 1 : 0;
+  d.spl = h.spl;
+  p->tune[PSATD_TUNE_FUSE_EB] = d.fuse;
   d.nF = h.itemsF.back();
   d.nU = h.itemsU.back();
   d.nI = h.itemsI.back();
@@ -531,7 +540,7 @@ psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
       HIPCHK(p, hipStreamSynchronize(p->stream));
       set_z_tile(p->h, value);
       HIPCHK(p, hipMemcpy(p->d_itemsU, p->h.itemsU.data(), p->h.itemsU.size() * 4, hipMemcpyHostToDevice));
-      HIPCHK(p, prepare_kernels(d.f64, p->h.ldsF, p->h.ldsI, p->h.ldsU, p->h.ldsX, p->h.ldsY));
+      HIPCHK(p, prepare_kernels(d.f64, d.spl, p->h.ldsF, p->h.ldsI, p->h.ldsU, p->h.ldsX, p->h.ldsY));
       d.PB = p->h.PB;
       d.ldsU = p->h.ldsU;
       d.nU = p->h.itemsU.back();
@@ -552,6 +561,19 @@ psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
       HIPCHK(p, hipStreamSynchronize(p->stream));
       set_batches(p->h, value);
       d.slab = p->h.batch_slab;
+      if (p->h.batches.size() > 1) {  // a later batch must still read its old guards
+        p->h.fuse_eb = false;
+        d.fuse = 0;
+        p->tune[PSATD_TUNE_FUSE_EB] = 0;
+      }
+      break;
+    }
+    case PSATD_TUNE_FUSE_EB: {
+      if (value != 0 && value != 1) return fail(p, PSATD_E_INVALID, "fuse must be 0 or 1");
+      if (value && p->h.batches.size() > 1)
+        return fail(p, PSATD_E_INVALID, "the fused E,B exchange needs all boxes in one batch");
+      p->h.fuse_eb = value != 0;
+      d.fuse = value;
       break;
     }
     case PSATD_TUNE_XCD_REMAP:
@@ -560,6 +582,7 @@ psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
       break;
     case PSATD_TUNE_MAX_RADIX: {
       if (value != 8 && value != 16) return fail(p, PSATD_E_INVALID, "max radix must be 8 or 16");
+      if (value != 16 && p->h.spl) return fail(p, PSATD_E_INVALID, "the matrix-core forms use radix <= 16");
       HostTables trial = p->h;
       if (!set_max_radix(trial, value))
         return fail(p, PSATD_E_INVALID, "a padded length has no schedule with this max radix");
@@ -583,7 +606,7 @@ psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
       break;
     default: {
       if (value < 0) return fail(p, PSATD_E_INVALID, "grid size must be >= 0");
-      static const int phase_of[] = {0, 0, kPhaseFwd, kPhaseUpd, kPhaseInv, kPhaseExchEB, 0, 0, 0, 0, 0};
+      static const int phase_of[] = {0, 0, kPhaseFwd, kPhaseUpd, kPhaseInv, kPhaseExchEB, 0, 0, 0, 0, 0, 0};
       d.grid_cap[phase_of[key]] = value;
       if (key == PSATD_TUNE_GRID_EXCH) d.grid_cap[kPhaseExchJ] = value;
     }

@@ -42,6 +42,18 @@ struct Batch {
   int64_t sbias;
 };
 
+// One rectangular piece of a box interior that is also a guard region of a
+// padded box (a neighbour's, or the box's own when its padding wraps the
+// grid): interior cells [z0, z0+lz) x [y0, y0+ly) x [x0, x0+lx) of the source
+// box are the padded cells starting at (qz, qy, qx) of box dst.  Every guard
+// cell of every box lies in exactly one piece of exactly one source box.
+struct PushBlk {
+  int32_t dst;
+  int32_t z0, lz, qz;
+  int32_t y0, ly, qy;
+  int32_t x0, lx, qx;
+};
+
 // Work list: item -> box by binary search in a prefix array (size nsub + 1).
 PSATD_HD int find_box(const int32_t* prefix, int nsub, int item) {
   int lo = 0, hi = nsub;  // prefix[lo] <= item < prefix[hi]
@@ -86,6 +98,32 @@ PSATD_HD void copy_batched(int total, int tid, int nt, Src src, Dst dst) {
   }
 }
 
+// Fused E,B guard exchange: after the inverse pass of interior plane zi (rows
+// [ya, yb) of it held by this work-group), write the new values into every
+// guard copy of those cells.  val(y, x) returns the new value of interior cell
+// (y, x).  The pieces of a source box are visited in a uniform loop; rows of a
+// piece are contiguous in the destination.
+template <typename T, class Val>
+PSATD_HD void push_guards(const PushBlk* blk, int b0, int b1, const BoxD* boxes, T* out, int zi,
+                          int ya, int yb, Val val, int tid, int nt) {
+  for (int b = b0; b < b1; ++b) {
+    const PushBlk k = blk[b];
+    if (zi < k.z0 || zi >= k.z0 + k.lz) continue;
+    const int y_lo = ya > k.y0 ? ya : k.y0;
+    const int y_hi = yb < k.y0 + k.ly ? yb : k.y0 + k.ly;
+    if (y_lo >= y_hi) continue;
+    const BoxD& d = boxes[k.dst];
+    T* base = out + d.foff + ((int64_t)(k.qz + zi - k.z0) * d.P[1] + (k.qy + y_lo - k.y0)) * d.P[0] + k.qx;
+    const int n = (y_hi - y_lo) * k.lx;
+    const FastDiv dl = make_fastdiv((uint32_t)k.lx);
+    for (int i = tid; i < n; i += nt) {
+      const int r = (int)fdiv((uint32_t)i, dl);
+      const int c = i - r * k.lx;
+      base[(int64_t)r * d.P[0] + c] = val(y_lo + r, k.x0 + c);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ pass F
 // Forward R2C along x and C2C along y of one z-plane of one field of one box.
 // Output: half spectrum plane [ky][kx] (kx = 0..H-1) in natural order.
@@ -102,8 +140,8 @@ struct FwdArgs {
 
 // LDS: the plane [y][x] with row stride ld, then the twiddles of the x plan
 // (Nh), the y plan (Py) and W_Px (real <-> half spectrum).
-template <typename T, int MAXR, class Bar>
-PSATD_HD void body_fwd_xy(const FwdArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar) {
+template <typename T, int MAXR, class Bar, class Eng = FftValu>
+PSATD_HD void body_fwd_xy(const FwdArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar, Eng eng = Eng{}) {
   const int s = find_box(a.items, a.t.nsub, item);
   const BoxD& bx = a.t.box[s];
   const int local = item - a.items[s];
@@ -148,7 +186,7 @@ PSATD_HD void body_fwd_xy(const FwdArgs<T>& a, int item, int tid, int nt, cx<T>*
                            }
                          });
   bar();
-  fft_dit<-1, MAXR>(lds, Py, ld, 1, plx, twx, tid, nt, bar);
+  eng.template dit<-1, MAXR>(lds, Py, ld, 1, plx, twx, tid, nt, bar);
   const int np = Nh / 2 + 1;
   const FastDiv dnp = make_fastdiv((uint32_t)np);
   for (int i = tid; i < Py * np; i += nt) {
@@ -156,7 +194,7 @@ PSATD_HD void body_fwd_xy(const FwdArgs<T>& a, int item, int tid, int nt, cx<T>*
     r2c_post(lds + y * ld, i - y * np, Nh, twr);
   }
   bar();
-  fft_dif<-1, MAXR>(lds, H, 1, ld, ply, twy, tid, nt, bar);
+  eng.template dif<-1, MAXR>(lds, H, 1, ld, ply, twy, tid, nt, bar);
   cx<T>* dst = a.spec + f * a.slab + (bx.soff - a.sbias) + (int64_t)z * Py * H;
   const FastDiv dH = make_fastdiv((uint32_t)H);
   copy_batched<8, cx<T>>(Py * H, tid, nt,
@@ -259,8 +297,8 @@ struct UpdArgs {
 // [z][f * PB + p] (W = 9 PB complex per z row), so that all 9 (then the 6
 // output) fields are transformed by one multi-transform pass with a uniform
 // element stride W.  Pencils past the end of the box (last block) are zeros.
-template <typename T, int PB, bool INC, int MAXR, class Bar>
-PSATD_HD void body_z_update(const UpdArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar) {
+template <typename T, int PB, bool INC, int MAXR, class Bar, class Eng = FftValu>
+PSATD_HD void body_z_update(const UpdArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar, Eng eng = Eng{}) {
   const int s = find_box(a.items, a.t.nsub, item);
   const BoxD& bx = a.t.box[s];
   const int blk = item - a.items[s];
@@ -300,7 +338,7 @@ PSATD_HD void body_z_update(const UpdArgs<T>& a, int item, int tid, int nt, cx<T
         lds[z * W + f * PB + p] = v;
       });
   bar();
-  fft_dif<-1, MAXR>(lds, 9 * PB, 1, W, plz, twz, tid, nt, bar);
+  eng.template dif<-1, MAXR>(lds, 9 * PB, 1, W, plz, twz, tid, nt, bar);
 
   const double* kxt = a.t.kmod + bx.kx;
   const double* kyt = a.t.kmod + bx.ky;
@@ -326,7 +364,7 @@ PSATD_HD void body_z_update(const UpdArgs<T>& a, int item, int tid, int nt, cx<T
     for (int f = 0; f < 6; ++f) row[f * PB] = cx<T>{vr[f], vi[f]};
   }
   bar();
-  fft_dit<+1, MAXR>(lds, 6 * PB, 1, W, plz, twz, tid, nt, bar);
+  eng.template dit<+1, MAXR>(lds, 6 * PB, 1, W, plz, twz, tid, nt, bar);
 
   cx<T>* dst = a.spec + (bx.soff - a.sbias) + q0;
   copy_batched<8, cx<T>>(6 * Pz * PB, tid, nt,
@@ -359,12 +397,14 @@ struct InvArgs {
   int64_t slab;
   int64_t sbias;
   T* out[6];
+  const PushBlk* push;       // fused E,B guard exchange (null: a separate fill pass)
+  const int32_t* push_off;   // pieces of box s: [push_off[s], push_off[s+1])
 };
 
 // LDS: the plane with row stride ld, then the twiddles of the y plan (Py),
 // the x plan (Nh) and W_Px.
-template <typename T, bool INC, int MAXR, class Bar>
-PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar) {
+template <typename T, bool INC, int MAXR, class Bar, class Eng = FftValu>
+PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar, Eng eng = Eng{}) {
   const int s = find_box(a.items, a.t.nsub, item);
   const BoxD& bx = a.t.box[s];
   const int local = item - a.items[s];
@@ -410,7 +450,7 @@ PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>*
                            }
                          });
   bar();
-  fft_dit<+1, MAXR>(lds, H, 1, ld, ply, twy, tid, nt, bar);
+  eng.template dit<+1, MAXR>(lds, H, 1, ld, ply, twy, tid, nt, bar);
   const int ny = bx.n[1], gy = bx.g[1];
   const int np = Nh / 2 + 1;
   const FastDiv dnp = make_fastdiv((uint32_t)np);
@@ -419,13 +459,15 @@ PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>*
     c2r_pre(lds + (gy + y) * ld, i - y * np, Nh, twr);
   }
   bar();
-  fft_dif<+1, MAXR>(lds + gy * ld, ny, ld, 1, plx, twx, tid, nt, bar);
+  eng.template dif<+1, MAXR>(lds + gy * ld, ny, ld, 1, plx, twx, tid, nt, bar);
   // 1/V applied in FP64 and rounded once: an FP32 1/V (not a power of two for
   // most V) would bias every step by the same relative amount.
   const double sc = 1.0 / ((double)Px * (double)Py * (double)Pz);
   const int nx = bx.n[0], gx = bx.g[0];
   T* dst = a.out[f] + bx.foff + (int64_t)z * Py * Px;
   const FastDiv dnx = make_fastdiv((uint32_t)nx);
+  T* ldsT = reinterpret_cast<T*>(lds);
+  const bool push = a.push_off != nullptr;
   copy_batched<8, T>(ny * nx, tid, nt,
                      [&](int i) {
                        const int yy = (int)fdiv((uint32_t)i, dnx);
@@ -435,9 +477,22 @@ PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>*
                      },
                      [&](int i, T v) {
                        const int yy = (int)fdiv((uint32_t)i, dnx);
-                       T* q = dst + (gy + yy) * Px + gx + (i - yy * nx);
-                       *q = INC ? *q + v : v;  // INC: v is the increment
+                       const int x = gx + (i - yy * nx);
+                       T* q = dst + (gy + yy) * Px + x;
+                       const T nv = INC ? *q + v : v;  // INC: v is the increment
+                       *q = nv;
+                       // the new value back into its own LDS slot for the guard copies
+                       if (push) ldsT[2 * ((gy + yy) * ld + posx[x >> 1]) + (x & 1)] = nv;
                      });
+  if (push) {
+    bar();
+    push_guards<T>(a.push, a.push_off[s], a.push_off[s + 1], a.t.box, a.out[f], z - bx.g[2], 0, ny,
+                   [&](int yi, int xi) {
+                     const int x = gx + xi;
+                     return ldsT[2 * ((gy + yi) * ld + posx[x >> 1]) + (x & 1)];
+                   },
+                   tid, nt);
+  }
 }
 
 // ------------------------------------------------ split x / y passes
@@ -456,11 +511,13 @@ struct SplitArgs {
   cx<T>* spec;
   int64_t slab;
   int64_t sbias;
+  const PushBlk* push;       // x inverse: fused E,B guard exchange (or null)
+  const int32_t* push_off;
 };
 
 // x forward: kRB rows of (box, z, field): packed real rows -> half spectrum rows.
-template <typename T, int MAXR, class Bar>
-PSATD_HD void body_x_fwd(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar) {
+template <typename T, int MAXR, class Bar, class Eng = FftValu>
+PSATD_HD void body_x_fwd(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar, Eng eng = Eng{}) {
   const int s = find_box(a.items, a.t.nsub, item);
   const BoxD& bx = a.t.box[s];
   const int Px = bx.P[0], Py = bx.P[1], Pz = bx.P[2];
@@ -498,7 +555,7 @@ PSATD_HD void body_x_fwd(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>
                            }
                          });
   bar();
-  fft_dit<-1, MAXR>(lds, ny, ld, 1, plx, twx, tid, nt, bar);
+  eng.template dit<-1, MAXR>(lds, ny, ld, 1, plx, twx, tid, nt, bar);
   const int np = Nh / 2 + 1;
   const FastDiv dnp = make_fastdiv((uint32_t)np);
   for (int i = tid; i < ny * np; i += nt) {
@@ -519,8 +576,8 @@ PSATD_HD void body_x_fwd(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>
 // y columns: kCB half-spectrum columns of (box, z, field), in place in the
 // workspace; DIR -1: forward over all planes and 9 fields; +1: inverse over
 // interior planes and the 6 outputs.
-template <typename T, int DIR, int MAXR, class Bar>
-PSATD_HD void body_y(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar) {
+template <typename T, int DIR, int MAXR, class Bar, class Eng = FftValu>
+PSATD_HD void body_y(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar, Eng eng = Eng{}) {
   const int s = find_box(a.items, a.t.nsub, item);
   const BoxD& bx = a.t.box[s];
   const int Py = bx.P[1], H = bx.H;
@@ -557,9 +614,9 @@ PSATD_HD void body_y(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>* ld
                          });
   bar();
   if (DIR < 0)
-    fft_dif<-1, MAXR>(lds, nc, 1, kCB, ply, twy, tid, nt, bar);
+    eng.template dif<-1, MAXR>(lds, nc, 1, kCB, ply, twy, tid, nt, bar);
   else
-    fft_dit<+1, MAXR>(lds, nc, 1, kCB, ply, twy, tid, nt, bar);
+    eng.template dit<+1, MAXR>(lds, nc, 1, kCB, ply, twy, tid, nt, bar);
   copy_batched<8, cx<T>>(ntot, tid, nt,
                          [&](int i) {
                            const int y = i / kCB, c = i % kCB;
@@ -573,8 +630,8 @@ PSATD_HD void body_y(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>* ld
 
 // x inverse: kRB interior rows of (box, interior z, output field):
 // half spectrum rows -> real rows, interior cells written (INC: added).
-template <typename T, bool INC, int MAXR, class Bar>
-PSATD_HD void body_x_inv(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar) {
+template <typename T, bool INC, int MAXR, class Bar, class Eng = FftValu>
+PSATD_HD void body_x_inv(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar, Eng eng = Eng{}) {
   const int s = find_box(a.items, a.t.nsub, item);
   const BoxD& bx = a.t.box[s];
   const int Px = bx.P[0], Py = bx.P[1], Pz = bx.P[2];
@@ -621,11 +678,13 @@ PSATD_HD void body_x_inv(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>
     c2r_pre(lds + y * ld, i - y * np, Nh, twr);
   }
   bar();
-  fft_dif<+1, MAXR>(lds, ny, ld, 1, plx, twx, tid, nt, bar);
+  eng.template dif<+1, MAXR>(lds, ny, ld, 1, plx, twx, tid, nt, bar);
   const double sc = 1.0 / ((double)Px * (double)Py * (double)Pz);
   const int nx = bx.n[0], gx = bx.g[0];
   T* dst = a.out[f] + bx.foff + ((int64_t)z * Py + y0) * Px;
   const FastDiv dnx = make_fastdiv((uint32_t)nx);
+  T* ldsT = reinterpret_cast<T*>(lds);
+  const bool push = a.push_off != nullptr;
   copy_batched<8, T>(ny * nx, tid, nt,
                      [&](int i) {
                        const int y = (int)fdiv((uint32_t)i, dnx);
@@ -635,9 +694,21 @@ PSATD_HD void body_x_inv(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>
                      },
                      [&](int i, T v) {
                        const int y = (int)fdiv((uint32_t)i, dnx);
-                       T* q = dst + y * Px + gx + (i - y * nx);
-                       *q = INC ? *q + v : v;
+                       const int x = gx + (i - y * nx);
+                       T* q = dst + y * Px + x;
+                       const T nv = INC ? *q + v : v;
+                       *q = nv;
+                       if (push) ldsT[2 * (y * ld + posx[x >> 1]) + (x & 1)] = nv;
                      });
+  if (push) {
+    bar();
+    push_guards<T>(a.push, a.push_off[s], a.push_off[s + 1], a.t.box, a.out[f], zz, yy0, yy0 + ny,
+                   [&](int yi, int xi) {
+                     const int x = gx + xi;
+                     return ldsT[2 * ((yi - yy0) * ld + posx[x >> 1]) + (x & 1)];
+                   },
+                   tid, nt);
+  }
 }
 
 // --------------------------------------------------------------- exchange

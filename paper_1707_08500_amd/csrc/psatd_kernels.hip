@@ -6,6 +6,9 @@
 // work-group per item or as a persistent grid.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
+#include "mfma_dft.hpp"
 #include "psatd_launch.hpp"
 
 namespace psatd {
@@ -15,6 +18,24 @@ struct BlockBarrier {
 };
 
 extern __shared__ __attribute__((aligned(16))) unsigned char psatd_lds[];
+
+// The matrix-core instruction of the split-BF16 DFT stage.
+struct MmaHw {
+  __device__ f32x4 operator()(bf16x8 a, bf16x8 b, f32x4 c) const {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+// FFT engine by precision form: SPL = 0 VALU radix stages; 2 or 3 BF16 terms
+// in a matrix-core first stage.
+template <int SPL>
+struct EngOf {
+  using type = FftMfma<SPL, MmaHw>;
+};
+template <>
+struct EngOf<0> {
+  using type = FftValu;
+};
 
 // Work-groups are dispatched round-robin over the 8 XCDs; with remap, block
 // b of the first 8*floor(G/8) takes item (b % 8) * (G/8) + b / 8 so that
@@ -29,56 +50,59 @@ __device__ __forceinline__ int first_item(int remap) {
   return b;
 }
 
-template <typename T, int NT, int MAXR>
+template <typename T, int NT, int MAXR, int SPL>
 __global__ __launch_bounds__(NT) void k_fwd_xy(FwdArgs<T> a, int item0, int nitems, int remap) {
   cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
   for (int it = first_item(remap); it < nitems; it += gridDim.x) {
-    body_fwd_xy<T, MAXR>(a, item0 + it, threadIdx.x, NT, lds, BlockBarrier{});
+    body_fwd_xy<T, MAXR>(a, item0 + it, threadIdx.x, NT, lds, BlockBarrier{}, typename EngOf<SPL>::type{});
     __syncthreads();
   }
 }
 
-template <typename T, bool INC, int NT, int MAXR>
+template <typename T, bool INC, int NT, int MAXR, int SPL>
 __global__ __launch_bounds__(NT) void k_inv_xy(InvArgs<T> a, int item0, int nitems, int remap) {
   cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
   for (int it = first_item(remap); it < nitems; it += gridDim.x) {
-    body_inv_xy<T, INC, MAXR>(a, item0 + it, threadIdx.x, NT, lds, BlockBarrier{});
+    body_inv_xy<T, INC, MAXR>(a, item0 + it, threadIdx.x, NT, lds, BlockBarrier{},
+                              typename EngOf<SPL>::type{});
     __syncthreads();
   }
 }
 
-template <typename T, int NT, int PB, bool INC, int MAXR>
+template <typename T, int NT, int PB, bool INC, int MAXR, int SPL>
 __global__ __launch_bounds__(NT) void k_z_update(UpdArgs<T> a, int item0, int nitems, int remap) {
   cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
   for (int it = first_item(remap); it < nitems; it += gridDim.x) {
-    body_z_update<T, PB, INC, MAXR>(a, item0 + it, threadIdx.x, NT, lds, BlockBarrier{});
+    body_z_update<T, PB, INC, MAXR>(a, item0 + it, threadIdx.x, NT, lds, BlockBarrier{},
+                                    typename EngOf<SPL>::type{});
     __syncthreads();
   }
 }
 
-template <typename T, int MAXR>
+template <typename T, int MAXR, int SPL>
 __global__ __launch_bounds__(kThreadsXY) void k_x_fwd(SplitArgs<T> a, int nitems, int remap) {
   cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
   for (int it = first_item(remap); it < nitems; it += gridDim.x) {
-    body_x_fwd<T, MAXR>(a, it, threadIdx.x, kThreadsXY, lds, BlockBarrier{});
+    body_x_fwd<T, MAXR>(a, it, threadIdx.x, kThreadsXY, lds, BlockBarrier{}, typename EngOf<SPL>::type{});
     __syncthreads();
   }
 }
 
-template <typename T, int DIR, int MAXR>
+template <typename T, int DIR, int MAXR, int SPL>
 __global__ __launch_bounds__(kThreadsXY) void k_y(SplitArgs<T> a, int nitems, int remap) {
   cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
   for (int it = first_item(remap); it < nitems; it += gridDim.x) {
-    body_y<T, DIR, MAXR>(a, it, threadIdx.x, kThreadsXY, lds, BlockBarrier{});
+    body_y<T, DIR, MAXR>(a, it, threadIdx.x, kThreadsXY, lds, BlockBarrier{}, typename EngOf<SPL>::type{});
     __syncthreads();
   }
 }
 
-template <typename T, bool INC, int MAXR>
+template <typename T, bool INC, int MAXR, int SPL>
 __global__ __launch_bounds__(kThreadsXY) void k_x_inv(SplitArgs<T> a, int nitems, int remap) {
   cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
   for (int it = first_item(remap); it < nitems; it += gridDim.x) {
-    body_x_inv<T, INC, MAXR>(a, it, threadIdx.x, kThreadsXY, lds, BlockBarrier{});
+    body_x_inv<T, INC, MAXR>(a, it, threadIdx.x, kThreadsXY, lds, BlockBarrier{},
+                             typename EngOf<SPL>::type{});
     __syncthreads();
   }
 }
@@ -140,14 +164,27 @@ static hipError_t set_lds(const void* f, int lds) {
   return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
-template <typename T, int MAXR>
+// Calls f(std::integral_constant<int, SPL>) for the plan's precision form;
+// the matrix-core forms exist for FP32 data only.
+template <typename T, class F>
+static hipError_t with_spl(int spl, F f) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (spl == 2) return f(std::integral_constant<int, 2>{});
+    if (spl == 3) return f(std::integral_constant<int, 3>{});
+  }
+  return f(std::integral_constant<int, 0>{});
+}
+
+template <typename T, int MAXR, int SPL>
 static hipError_t prepare_t(int ldsF, int ldsI, int ldsU, int ldsX, int ldsY) {
   constexpr bool I = IncOf<T>::value;
-  const void* xy[] = {(const void*)k_fwd_xy<T, 256, MAXR>, (const void*)k_fwd_xy<T, 512, MAXR>};
-  const void* inv[] = {(const void*)k_inv_xy<T, I, 256, MAXR>, (const void*)k_inv_xy<T, I, 512, MAXR>};
-  const void* upd[] = {(const void*)k_z_update<T, 512, 8, I, MAXR>, (const void*)k_z_update<T, 512, 16, I, MAXR>,
-                       (const void*)k_z_update<T, 1024, 8, I, MAXR>, (const void*)k_z_update<T, 1024, 16, I, MAXR>,
-                       (const void*)k_z_update<T, 512, 4, I, MAXR>};
+  const void* xy[] = {(const void*)k_fwd_xy<T, 256, MAXR, SPL>, (const void*)k_fwd_xy<T, 512, MAXR, SPL>};
+  const void* inv[] = {(const void*)k_inv_xy<T, I, 256, MAXR, SPL>, (const void*)k_inv_xy<T, I, 512, MAXR, SPL>};
+  const void* upd[] = {(const void*)k_z_update<T, 512, 8, I, MAXR, SPL>,
+                       (const void*)k_z_update<T, 512, 16, I, MAXR, SPL>,
+                       (const void*)k_z_update<T, 1024, 8, I, MAXR, SPL>,
+                       (const void*)k_z_update<T, 1024, 16, I, MAXR, SPL>,
+                       (const void*)k_z_update<T, 512, 4, I, MAXR, SPL>};
   hipError_t e;
   for (const void* f : xy)
     if (ldsF <= kMaxDynLds && (e = set_lds(f, ldsF)) != hipSuccess) return e;
@@ -155,20 +192,22 @@ static hipError_t prepare_t(int ldsF, int ldsI, int ldsU, int ldsX, int ldsY) {
     if (ldsI <= kMaxDynLds && (e = set_lds(f, ldsI)) != hipSuccess) return e;
   for (const void* f : upd)
     if ((e = set_lds(f, ldsU)) != hipSuccess) return e;
-  if ((e = set_lds((const void*)k_x_fwd<T, MAXR>, ldsX)) != hipSuccess) return e;
-  if ((e = set_lds((const void*)k_x_inv<T, I, MAXR>, ldsX)) != hipSuccess) return e;
-  if ((e = set_lds((const void*)k_y<T, -1, MAXR>, ldsY)) != hipSuccess) return e;
-  return set_lds((const void*)k_y<T, 1, MAXR>, ldsY);
+  if ((e = set_lds((const void*)k_x_fwd<T, MAXR, SPL>, ldsX)) != hipSuccess) return e;
+  if ((e = set_lds((const void*)k_x_inv<T, I, MAXR, SPL>, ldsX)) != hipSuccess) return e;
+  if ((e = set_lds((const void*)k_y<T, -1, MAXR, SPL>, ldsY)) != hipSuccess) return e;
+  return set_lds((const void*)k_y<T, 1, MAXR, SPL>, ldsY);
 }
 
-hipError_t prepare_kernels(bool f64, int ldsF, int ldsI, int ldsU, int ldsX, int ldsY) {
+hipError_t prepare_kernels(bool f64, int spl, int ldsF, int ldsI, int ldsU, int ldsX, int ldsY) {
   hipError_t e;
   if (f64) {
-    if ((e = prepare_t<double, 8>(ldsF, ldsI, ldsU, ldsX, ldsY)) != hipSuccess) return e;
-    return prepare_t<double, 16>(ldsF, ldsI, ldsU, ldsX, ldsY);
+    if ((e = prepare_t<double, 8, 0>(ldsF, ldsI, ldsU, ldsX, ldsY)) != hipSuccess) return e;
+    return prepare_t<double, 16, 0>(ldsF, ldsI, ldsU, ldsX, ldsY);
   }
-  if ((e = prepare_t<float, 8>(ldsF, ldsI, ldsU, ldsX, ldsY)) != hipSuccess) return e;
-  return prepare_t<float, 16>(ldsF, ldsI, ldsU, ldsX, ldsY);
+  if (spl == 2) return prepare_t<float, 16, 2>(ldsF, ldsI, ldsU, ldsX, ldsY);
+  if (spl == 3) return prepare_t<float, 16, 3>(ldsF, ldsI, ldsU, ldsX, ldsY);
+  if ((e = prepare_t<float, 8, 0>(ldsF, ldsI, ldsU, ldsX, ldsY)) != hipSuccess) return e;
+  return prepare_t<float, 16, 0>(ldsF, ldsI, ldsU, ldsX, ldsY);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -211,6 +250,24 @@ hipError_t launch_sum(const DevPlan& p, void* const* J, hipStream_t st) {
   return p.f64 ? sum_t<double>(p, J, st) : sum_t<float>(p, J, st);
 }
 
+// MAXR = 8 kernels exist for the VALU form only.
+#define PSATD_MAXR_SWITCH(SPL, CALL8, CALL16) \
+  do {                                         \
+    if constexpr ((SPL) > 0) {                 \
+      CALL16;                                  \
+    } else if (p.maxr >= 16) {                 \
+      CALL16;                                  \
+    } else {                                   \
+      CALL8;                                   \
+    }                                          \
+  } while (0)
+
+template <typename T, int NT, int MAXR, int SPL>
+static hipError_t fwd_go(const DevPlan& p, const Batch& b, const FwdArgs<T>& a, int g, hipStream_t st) {
+  hipLaunchKernelGGL((k_fwd_xy<T, NT, MAXR, SPL>), dim3(g), dim3(NT), p.ldsF, st, a, b.F0, b.nF, p.xcd);
+  return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t fwd_t(const DevPlan& p, const Batch& b, void* const* in9, void* spec, hipStream_t st) {
   FwdArgs<T> a;
@@ -223,37 +280,36 @@ static hipError_t fwd_t(const DevPlan& p, const Batch& b, void* const* in9, void
   a.sbias = b.sbias;
   const int g = grid_for(b.nF, p.grid_cap[kPhaseFwd]);
   if (!g) return hipSuccess;
-  if (p.ntxy == 512) {
-    if (p.maxr >= 16)
-      hipLaunchKernelGGL((k_fwd_xy<T, 512, 16>), dim3(g), dim3(512), p.ldsF, st, a, b.F0, b.nF, p.xcd);
-    else
-      hipLaunchKernelGGL((k_fwd_xy<T, 512, 8>), dim3(g), dim3(512), p.ldsF, st, a, b.F0, b.nF, p.xcd);
-  } else {
-    if (p.maxr >= 16)
-      hipLaunchKernelGGL((k_fwd_xy<T, 256, 16>), dim3(g), dim3(256), p.ldsF, st, a, b.F0, b.nF, p.xcd);
-    else
-      hipLaunchKernelGGL((k_fwd_xy<T, 256, 8>), dim3(g), dim3(256), p.ldsF, st, a, b.F0, b.nF, p.xcd);
-  }
-  return hipGetLastError();
+  return with_spl<T>(p.spl, [&](auto sc) -> hipError_t {
+    constexpr int SPL = decltype(sc)::value;
+    if (p.ntxy == 512)
+      PSATD_MAXR_SWITCH(SPL, return (fwd_go<T, 512, 8, SPL>(p, b, a, g, st)),
+                        return (fwd_go<T, 512, 16, SPL>(p, b, a, g, st)));
+    PSATD_MAXR_SWITCH(SPL, return (fwd_go<T, 256, 8, SPL>(p, b, a, g, st)),
+                      return (fwd_go<T, 256, 16, SPL>(p, b, a, g, st)));
+    return hipSuccess;
+  });
 }
 
 hipError_t launch_fwd(const DevPlan& p, const Batch& b, void* const* in9, void* spec, hipStream_t st) {
   return p.f64 ? fwd_t<double>(p, b, in9, spec, st) : fwd_t<float>(p, b, in9, spec, st);
 }
 
-template <typename T, int NT, int PB, int MAXR>
+template <typename T, int NT, int PB, int MAXR, int SPL>
 static hipError_t upd_launch(const DevPlan& p, const Batch& b, const UpdArgs<T>& a, int g, hipStream_t st) {
-  hipLaunchKernelGGL((k_z_update<T, NT, PB, IncOf<T>::value, MAXR>), dim3(g), dim3(NT), p.ldsU, st, a,
+  hipLaunchKernelGGL((k_z_update<T, NT, PB, IncOf<T>::value, MAXR, SPL>), dim3(g), dim3(NT), p.ldsU, st, a,
                      b.U0, b.nU, p.xcd);
   return hipGetLastError();
 }
 
-template <typename T, int MAXR>
+template <typename T, int MAXR, int SPL>
 static hipError_t upd_shape(const DevPlan& p, const Batch& b, const UpdArgs<T>& a, int g, hipStream_t st) {
-  if (p.PB == 4) return upd_launch<T, 512, 4, MAXR>(p, b, a, g, st);
+  if (p.PB == 4) return upd_launch<T, 512, 4, MAXR, SPL>(p, b, a, g, st);
   if (p.ntu == 1024)
-    return p.PB == 16 ? upd_launch<T, 1024, 16, MAXR>(p, b, a, g, st) : upd_launch<T, 1024, 8, MAXR>(p, b, a, g, st);
-  return p.PB == 16 ? upd_launch<T, 512, 16, MAXR>(p, b, a, g, st) : upd_launch<T, 512, 8, MAXR>(p, b, a, g, st);
+    return p.PB == 16 ? upd_launch<T, 1024, 16, MAXR, SPL>(p, b, a, g, st)
+                      : upd_launch<T, 1024, 8, MAXR, SPL>(p, b, a, g, st);
+  return p.PB == 16 ? upd_launch<T, 512, 16, MAXR, SPL>(p, b, a, g, st)
+                    : upd_launch<T, 512, 8, MAXR, SPL>(p, b, a, g, st);
 }
 
 template <typename T>
@@ -268,11 +324,23 @@ static hipError_t upd_t(const DevPlan& p, const Batch& b, void* spec, hipStream_
   a.k.dt = p.dt;
   const int g = grid_for(b.nU, p.grid_cap[kPhaseUpd]);
   if (!g) return hipSuccess;
-  return p.maxr >= 16 ? upd_shape<T, 16>(p, b, a, g, st) : upd_shape<T, 8>(p, b, a, g, st);
+  return with_spl<T>(p.spl, [&](auto sc) -> hipError_t {
+    constexpr int SPL = decltype(sc)::value;
+    PSATD_MAXR_SWITCH(SPL, return (upd_shape<T, 8, SPL>(p, b, a, g, st)),
+                      return (upd_shape<T, 16, SPL>(p, b, a, g, st)));
+    return hipSuccess;
+  });
 }
 
 hipError_t launch_upd(const DevPlan& p, const Batch& b, void* spec, hipStream_t st) {
   return p.f64 ? upd_t<double>(p, b, spec, st) : upd_t<float>(p, b, spec, st);
+}
+
+template <typename T, int NT, int MAXR, int SPL>
+static hipError_t inv_go(const DevPlan& p, const Batch& b, const InvArgs<T>& a, int g, hipStream_t st) {
+  hipLaunchKernelGGL((k_inv_xy<T, IncOf<T>::value, NT, MAXR, SPL>), dim3(g), dim3(NT), p.ldsI, st, a, b.I0,
+                     b.nI, p.xcd);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -284,21 +352,19 @@ static hipError_t inv_t(const DevPlan& p, const Batch& b, const void* spec, void
   a.slab = p.slab;
   a.sbias = b.sbias;
   for (int f = 0; f < 6; ++f) a.out[f] = reinterpret_cast<T*>(out6[f]);
+  a.push = p.fuse ? p.push : nullptr;
+  a.push_off = p.fuse ? p.push_off : nullptr;
   const int g = grid_for(b.nI, p.grid_cap[kPhaseInv]);
   if (!g) return hipSuccess;
-  constexpr bool I = IncOf<T>::value;
-  if (p.ntxy == 512) {
-    if (p.maxr >= 16)
-      hipLaunchKernelGGL((k_inv_xy<T, I, 512, 16>), dim3(g), dim3(512), p.ldsI, st, a, b.I0, b.nI, p.xcd);
-    else
-      hipLaunchKernelGGL((k_inv_xy<T, I, 512, 8>), dim3(g), dim3(512), p.ldsI, st, a, b.I0, b.nI, p.xcd);
-  } else {
-    if (p.maxr >= 16)
-      hipLaunchKernelGGL((k_inv_xy<T, I, 256, 16>), dim3(g), dim3(256), p.ldsI, st, a, b.I0, b.nI, p.xcd);
-    else
-      hipLaunchKernelGGL((k_inv_xy<T, I, 256, 8>), dim3(g), dim3(256), p.ldsI, st, a, b.I0, b.nI, p.xcd);
-  }
-  return hipGetLastError();
+  return with_spl<T>(p.spl, [&](auto sc) -> hipError_t {
+    constexpr int SPL = decltype(sc)::value;
+    if (p.ntxy == 512)
+      PSATD_MAXR_SWITCH(SPL, return (inv_go<T, 512, 8, SPL>(p, b, a, g, st)),
+                        return (inv_go<T, 512, 16, SPL>(p, b, a, g, st)));
+    PSATD_MAXR_SWITCH(SPL, return (inv_go<T, 256, 8, SPL>(p, b, a, g, st)),
+                      return (inv_go<T, 256, 16, SPL>(p, b, a, g, st)));
+    return hipSuccess;
+  });
 }
 
 hipError_t launch_inv(const DevPlan& p, const Batch& b, const void* spec, void* const* out6, hipStream_t st) {
@@ -315,6 +381,8 @@ static SplitArgs<T> split_args(const DevPlan& p, void* spec) {
   a.spec = reinterpret_cast<cx<T>*>(spec);
   a.slab = p.slab;
   a.sbias = 0;
+  a.push = p.fuse ? p.push : nullptr;
+  a.push_off = p.fuse ? p.push_off : nullptr;
   return a;
 }
 
@@ -325,11 +393,15 @@ static hipError_t x_fwd_t(const DevPlan& p, void* const* in9, void* spec, hipStr
   for (int f = 0; f < 9; ++f) a.in[f] = reinterpret_cast<const T*>(in9[f]);
   const int g = grid_for(p.nXF, p.grid_cap[kPhaseFwd]);
   if (!g) return hipSuccess;
-  if (p.maxr >= 16)
-    hipLaunchKernelGGL((k_x_fwd<T, 16>), dim3(g), dim3(kThreadsXY), p.ldsX, st, a, p.nXF, p.xcd);
-  else
-    hipLaunchKernelGGL((k_x_fwd<T, 8>), dim3(g), dim3(kThreadsXY), p.ldsX, st, a, p.nXF, p.xcd);
-  return hipGetLastError();
+  return with_spl<T>(p.spl, [&](auto sc) -> hipError_t {
+    constexpr int SPL = decltype(sc)::value;
+    PSATD_MAXR_SWITCH(SPL,
+                      hipLaunchKernelGGL((k_x_fwd<T, 8, SPL>), dim3(g), dim3(kThreadsXY), p.ldsX, st, a,
+                                         p.nXF, p.xcd),
+                      hipLaunchKernelGGL((k_x_fwd<T, 16, SPL>), dim3(g), dim3(kThreadsXY), p.ldsX, st, a,
+                                         p.nXF, p.xcd));
+    return hipGetLastError();
+  });
 }
 
 template <typename T>
@@ -339,18 +411,22 @@ static hipError_t y_t(const DevPlan& p, int dir, void* spec, hipStream_t st) {
   const int n = dir < 0 ? p.nYF : p.nYI;
   const int g = grid_for(n, p.grid_cap[dir < 0 ? kPhaseFwd : kPhaseInv]);
   if (!g) return hipSuccess;
-  if (dir < 0) {
-    if (p.maxr >= 16)
-      hipLaunchKernelGGL((k_y<T, -1, 16>), dim3(g), dim3(kThreadsXY), p.ldsY, st, a, n, p.xcd);
+  return with_spl<T>(p.spl, [&](auto sc) -> hipError_t {
+    constexpr int SPL = decltype(sc)::value;
+    if (dir < 0)
+      PSATD_MAXR_SWITCH(SPL,
+                        hipLaunchKernelGGL((k_y<T, -1, 8, SPL>), dim3(g), dim3(kThreadsXY), p.ldsY, st, a, n,
+                                           p.xcd),
+                        hipLaunchKernelGGL((k_y<T, -1, 16, SPL>), dim3(g), dim3(kThreadsXY), p.ldsY, st, a, n,
+                                           p.xcd));
     else
-      hipLaunchKernelGGL((k_y<T, -1, 8>), dim3(g), dim3(kThreadsXY), p.ldsY, st, a, n, p.xcd);
-  } else {
-    if (p.maxr >= 16)
-      hipLaunchKernelGGL((k_y<T, 1, 16>), dim3(g), dim3(kThreadsXY), p.ldsY, st, a, n, p.xcd);
-    else
-      hipLaunchKernelGGL((k_y<T, 1, 8>), dim3(g), dim3(kThreadsXY), p.ldsY, st, a, n, p.xcd);
-  }
-  return hipGetLastError();
+      PSATD_MAXR_SWITCH(SPL,
+                        hipLaunchKernelGGL((k_y<T, 1, 8, SPL>), dim3(g), dim3(kThreadsXY), p.ldsY, st, a, n,
+                                           p.xcd),
+                        hipLaunchKernelGGL((k_y<T, 1, 16, SPL>), dim3(g), dim3(kThreadsXY), p.ldsY, st, a, n,
+                                           p.xcd));
+    return hipGetLastError();
+  });
 }
 
 template <typename T>
@@ -361,12 +437,18 @@ static hipError_t x_inv_t(const DevPlan& p, const void* spec, void* const* out6,
   const int g = grid_for(p.nXI, p.grid_cap[kPhaseInv]);
   if (!g) return hipSuccess;
   constexpr bool I = IncOf<T>::value;
-  if (p.maxr >= 16)
-    hipLaunchKernelGGL((k_x_inv<T, I, 16>), dim3(g), dim3(kThreadsXY), p.ldsX, st, a, p.nXI, p.xcd);
-  else
-    hipLaunchKernelGGL((k_x_inv<T, I, 8>), dim3(g), dim3(kThreadsXY), p.ldsX, st, a, p.nXI, p.xcd);
-  return hipGetLastError();
+  return with_spl<T>(p.spl, [&](auto sc) -> hipError_t {
+    constexpr int SPL = decltype(sc)::value;
+    PSATD_MAXR_SWITCH(SPL,
+                      hipLaunchKernelGGL((k_x_inv<T, I, 8, SPL>), dim3(g), dim3(kThreadsXY), p.ldsX, st, a,
+                                         p.nXI, p.xcd),
+                      hipLaunchKernelGGL((k_x_inv<T, I, 16, SPL>), dim3(g), dim3(kThreadsXY), p.ldsX, st, a,
+                                         p.nXI, p.xcd));
+    return hipGetLastError();
+  });
 }
+
+#undef PSATD_MAXR_SWITCH
 
 hipError_t launch_x_fwd(const DevPlan& p, void* const* in9, void* spec, hipStream_t st) {
   return p.f64 ? x_fwd_t<double>(p, in9, spec, st) : x_fwd_t<float>(p, in9, spec, st);

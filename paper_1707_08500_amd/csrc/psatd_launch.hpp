@@ -32,6 +32,10 @@ struct DevPlan {
   int32_t nXF, nYF, nYI, nXI;
   int32_t ldsX, ldsY;
   int32_t split;
+  const PushBlk* push;       // guard pieces of the fused E,B exchange
+  const int32_t* push_off;
+  int32_t fuse;              // 1: the inverse pass writes the E,B guard copies
+  int32_t spl;               // BF16 terms of the matrix-core DFT stage (0: VALU only)
   int32_t nF, nU, nI, nP, nN;
   int32_t ldsF, ldsI, ldsU;  // dynamic LDS bytes per work-group
   int32_t PB;                // pencils per z-update work-group
@@ -57,7 +61,7 @@ hipError_t launch_scatter(const DevPlan& p, const void* const* glob, void* const
 hipError_t launch_gather(const DevPlan& p, const void* const* pad, void* const* glob, hipStream_t st);
 hipError_t launch_modk(const KEntry* entries, int nent, int maxN, int order_p, double* kmod,
                        hipStream_t st);
-hipError_t prepare_kernels(bool f64, int ldsF, int ldsI, int ldsU, int ldsX, int ldsY);
+hipError_t prepare_kernels(bool f64, int spl, int ldsF, int ldsI, int ldsU, int ldsX, int ldsY);
 
 
 }  // namespace psatd

@@ -94,11 +94,17 @@ def test_validate_prime_factor_and_parity():
     with pytest.raises(psatd.PsatdError) as ei:
         psatd.validate((9, 8, 8), (1, 1, 1), [[0, 0, 0]], [[9, 8, 8]], [[0, 0, 0]], 0, 0.5)
     assert ei.value.status == 4
-    # split-BF16 forms are reported as unsupported, not silently mapped
-    with pytest.raises(psatd.PsatdError) as ei:
-        psatd.validate((32, 32, 32), (1, 1, 1), [[0, 0, 0]], [[32, 32, 32]], [[0, 0, 0]], 0, 0.5,
-                       precision="bf16x3")
-    assert ei.value.status == 4
+    # the split-BF16 forms plan like FP32 (FP32 buffers); an unknown form is rejected
+    for form in ("bf16x3", "bf16x6"):
+        assert psatd.validate((32, 32, 32), (1, 1, 1), [[0, 0, 0]], [[32, 32, 32]], [[0, 0, 0]], 0,
+                              0.5, precision=form) == 32 ** 3
+    gn = (ctypes.c_int64 * 3)(8, 8, 8)
+    gd = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
+    lo = (ctypes.c_int64 * 3)(0, 0, 0)
+    nn = (ctypes.c_int64 * 3)(8, 8, 8)
+    gg = (ctypes.c_int32 * 3)(0, 0, 0)
+    out = ctypes.c_int64(0)
+    assert psatd.LIB.psatd_validate(gn, gd, 1, lo, nn, gg, 0, 0.5, 1.0, 7, 0, ctypes.byref(out)) == 1
 
 
 def test_null_and_bad_plan_calls_are_errors_not_crashes():
