@@ -189,9 +189,28 @@ def summarize_ktrace(stats_csv, bench_line, workload, command):
     return "\n".join(lines) + "\n"
 
 
-def read_traffic(workload, kernel):
-    """Scaled HBM bytes per dispatch of `kernel` from the committed summary, or
-    None when there is none or it was taken on other kernel sources."""
+SPL_OF = {"f32": 0, "bf16x3": 2, "bf16x6": 3}
+
+
+def kernel_instance(phase, form, tuning):
+    """The template instance (as the profiler prints it) that runs `phase` for
+    the FP32 form `form` with launch shapes `tuning` (unsplit x/y passes)."""
+    spl = SPL_OF[form]
+    maxr = 16 if spl else tuning["max_radix"]
+    if phase == "z_update":
+        pb = tuning["z_pencils"]
+        nt = 512 if pb == 4 else tuning["z_threads"]
+        return f"psatd::k_z_update<float, {nt}, {pb}, true, {maxr}, {spl}>"
+    if phase == "fft_xy_fwd":
+        return f"psatd::k_fwd_xy<float, {tuning['xy_threads']}, {maxr}, {spl}>"
+    if phase == "fft_xy_inv":
+        return f"psatd::k_inv_xy<float, true, {tuning['xy_threads']}, {maxr}, {spl}>"
+    return "psatd::k_fill<float>"
+
+
+def read_traffic(workload, instance):
+    """Scaled HBM bytes per dispatch of the kernel instance from the committed
+    summary, or None when there is none or it was taken on other sources."""
     path = traffic_path(workload)
     if not os.path.exists(path):
         return None
@@ -201,8 +220,8 @@ def read_traffic(workload, kernel):
             digest = line.split(":", 1)[1].strip()
         elif line.startswith("kernel "):
             fields = [f.strip() for f in line[len("kernel "):].split("|")]
-            if fields[0].split("<")[0].split("::")[-1] == kernel:
-                found = float(fields[4]) if found is None else max(found, float(fields[4]))
+            if fields[0] == instance:
+                found = float(fields[4])
     if digest != source_digest():
         return None
     return found
@@ -386,7 +405,9 @@ def main():
         },
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": read_traffic(args.workload, PHASE_KERNEL[dom]) if head == "f32" else None,
+                     "kernel_instance": kernel_instance(dom, head, r32["tuning"]),
+                     "traffic": (read_traffic(args.workload, kernel_instance(dom, head, r32["tuning"]))
+                                 if not r32["tuning"]["split_xy"] else None),
                      "algorithmic_bytes": r32["algo_bytes"][dom]},
         "fp32_forms": {f: {k: results[f][k] for k in ("value", "ms_per_step", "rel_l2_vs_fp64",
                                                       "rel_l2_vs_fp64_max", "phases_ms")

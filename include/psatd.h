@@ -183,6 +183,22 @@ psatd_status psatd_run(psatd_plan_t plan, void* const E[3], void* const B[3], vo
                        int32_t nsteps);
 
 /*
+ * psatd_heat_run -- nsteps >= 0 steps of the same local-FFT method applied to the
+ * diffusion equation du/dt = D lap u (Sec. 5 names it among the initial-value problems
+ * the method extends to): every padded box advanced by its exact propagator
+ * u <- IFFT(exp(-D |[k]|^2 dt) FFT(u)), with the plan's order-p modified wavenumbers
+ * (Sec. 3.1) and dt, then every guard copy of u takes its owner's value (Fig. 3).
+ *   u            ONE device buffer of psatd_field_elems elements in the plan's layout and
+ *                dtype (the F32 forms: float, the propagator applied to the increment),
+ *                consistent on entry (psatd_scatter of a component does that) and on exit
+ *   diffusivity  D >= 0, finite
+ * Enqueued on the plan's stream (no graph).  Uses the plan's workspace.  Errors:
+ * PSATD_E_UNSUPPORTED when the padded planes need the split x/y passes; PSATD_E_STATE
+ * when the plan is batched (PSATD_TUNE_BATCH_BOXES).
+ */
+psatd_status psatd_heat_run(psatd_plan_t plan, void* u, double diffusivity, int32_t nsteps);
+
+/*
  * psatd_run_profiled -- nsteps >= 1 steps (psatd_step semantics, J exchanged every step)
  * launched directly with a HIP event pair around every kernel launch; waits for
  * completion and writes the mean milliseconds per step of each phase to

@@ -165,6 +165,12 @@ psatd_status enqueue_step(psatd_plan_t p, void* const E[3], void* const B[3], vo
   return PSATD_OK;
 }
 
+// LDS of the heat z pass: PB staged pencils, the z twiddles and z indices.
+int32_t heat_lds(const HostTables& h) {
+  const int maxPz = max_padded_z(h);
+  return (int32_t)((int64_t)maxPz * (h.PB + 1) * (int64_t)(2 * real_size(h.prec)) + (int64_t)maxPz * 4);
+}
+
 psatd_status check_step_args(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3]) {
   if (!p) return fail(nullptr, PSATD_E_INVALID, "null plan");
   psatd_status r;
@@ -360,6 +366,7 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   d.ldsI = h.ldsI;
   d.ldsU = h.ldsU;
   d.PB = h.PB;
+  d.ldsH = heat_lds(h);
   d.ntu = h.ntu;
   d.ntxy = h.ntxy;
   d.maxr = h.maxr;
@@ -459,6 +466,30 @@ psatd_status psatd_run(psatd_plan_t p, void* const E[3], void* const B[3], void*
   return PSATD_OK;
 }
 
+psatd_status psatd_heat_run(psatd_plan_t p, void* u, double diffusivity, int32_t nsteps) {
+  if (!p) return fail(nullptr, PSATD_E_INVALID, "null plan");
+  void* one[1] = {u};
+  psatd_status r = check_fields(p, one, 1, "u");
+  if (r != PSATD_OK) return r;
+  if (!(diffusivity >= 0.0) || !std::isfinite(diffusivity))
+    return fail(p, PSATD_E_INVALID, "diffusivity must be finite and >= 0");
+  if (nsteps < 0) return fail(p, PSATD_E_INVALID, "nsteps < 0");
+  if (p->dp.split) return fail(p, PSATD_E_UNSUPPORTED, "the heat step needs padded planes that fit the LDS");
+  if (p->h.batches.size() != 1) return fail(p, PSATD_E_STATE, "the heat step needs all boxes in one batch");
+  if ((r = ensure_workspace(p)) != PSATD_OK) return r;
+  const DevPlan& d = p->dp;
+  const Batch all{0, d.nsub, 0, d.nP, 0, d.nU, 0, d.nN, 0};
+  void* in9[9] = {u, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  void* out6[6] = {u, nullptr, nullptr, nullptr, nullptr, nullptr};
+  for (int i = 0; i < nsteps; ++i) {
+    HIPCHK(p, launch_fwd(d, all, in9, p->ws, p->stream, true));
+    HIPCHK(p, launch_heat_z(d, p->ws, diffusivity, d.dt, p->stream));
+    HIPCHK(p, launch_inv(d, all, p->ws, out6, p->stream, true));
+    HIPCHK(p, launch_fill(d, out6, 1, p->stream));
+  }
+  return PSATD_OK;
+}
+
 psatd_status psatd_run_profiled(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3],
                                 int32_t nsteps, double* phase_ms) {
   psatd_status r = check_step_args(p, E, B, J);
@@ -543,6 +574,7 @@ psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
       HIPCHK(p, prepare_kernels(d.f64, d.spl, p->h.ldsF, p->h.ldsI, p->h.ldsU, p->h.ldsX, p->h.ldsY));
       d.PB = p->h.PB;
       d.ldsU = p->h.ldsU;
+      d.ldsH = heat_lds(p->h);
       d.nU = p->h.itemsU.back();
       break;
     }

@@ -386,6 +386,75 @@ PSATD_HD void body_z_update(const UpdArgs<T>& a, int item, int tid, int nt, cx<T
       });
 }
 
+// ------------------------------------------------------- heat equation
+// Sec. 5 names the diffusion equation among the initial-value problems the
+// local-FFT method applies to: du/dt = D lap u, Laplacian symbol -|[k]|^2 with
+// the same order-p modified wavenumbers, exact propagator per step.  The x/y
+// passes are the field passes with one field; this is its z pass.
+template <typename T>
+struct HeatArgs {
+  Tables<T> t;
+  const int32_t* items;  // prefix over boxes of ceil(P[1] H / PB)
+  cx<T>* spec;           // the half spectrum of u
+  double D, dt;
+};
+
+// PB consecutive (ky, kx) pencils staged as [z][p]: forward z transform,
+// multiply by g = exp(-D |[k]|^2 dt) in FP64 (INC: by g - 1 = expm1(...), the
+// increment's spectrum), inverse z transform.
+template <typename T, int PB, bool INC, int MAXR, class Bar, class Eng = FftValu>
+PSATD_HD void body_z_heat(const HeatArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar,
+                          Eng eng = Eng{}) {
+  const int s = find_box(a.items, a.t.nsub, item);
+  const BoxD& bx = a.t.box[s];
+  const int blk = item - a.items[s];
+  const int Py = bx.P[1], Pz = bx.P[2], H = bx.H;
+  const int nq = Py * H;
+  const int q0 = blk * PB;
+  const int np = (nq - q0) < PB ? (nq - q0) : PB;
+  const FftPlanD* plz = a.t.plans + bx.planz;
+  cx<T>* twz = lds + Pz * PB;
+  int32_t* kzi = reinterpret_cast<int32_t*>(twz + Pz);
+  const cx<T>* gtz = a.t.tw + plz->tw;
+  for (int i = tid; i < Pz; i += nt) kzi[i] = plan_index(plz, i);
+  cx<T>* col = a.spec + bx.soff + q0;
+  const int ndata = Pz * PB;
+  copy_batched<8, cx<T>>(ndata + Pz, tid, nt,
+      [&](int i) {
+        if (i >= ndata) return gtz[i - ndata];
+        const int p = i % PB;
+        return (p < np) ? col[(int64_t)(i / PB) * nq + p] : cx<T>{T(0), T(0)};
+      },
+      [&](int i, cx<T> v) {
+        if (i >= ndata) twz[i - ndata] = v;
+        else lds[i] = v;
+      });
+  bar();
+  eng.template dif<-1, MAXR>(lds, PB, 1, PB, plz, twz, tid, nt, bar);
+  const double* kxt = a.t.kmod + bx.kx;
+  const double* kyt = a.t.kmod + bx.ky;
+  const double* kzt = a.t.kmod + bx.kz;
+  const FastDiv dH = make_fastdiv((uint32_t)H);
+  for (int i = tid; i < ndata; i += nt) {
+    const int p = i % PB;
+    if (p >= np) continue;
+    const int q = q0 + p;
+    const int ky = (int)fdiv((uint32_t)q, dH);
+    const int kx = q - ky * H;
+    const double k1 = kxt[kx], k2 = kyt[ky], k3 = kzt[kzi[i / PB]];
+    const double e = -a.D * (k1 * k1 + k2 * k2 + k3 * k3) * a.dt;
+    const T g = (T)(INC ? expm1(e) : exp(e));
+    lds[i] = cx<T>{lds[i].x * g, lds[i].y * g};
+  }
+  bar();
+  eng.template dit<+1, MAXR>(lds, PB, 1, PB, plz, twz, tid, nt, bar);
+  copy_batched<8, cx<T>>(ndata, tid, nt, [&](int i) { return lds[i]; },
+                         [&](int i, cx<T> v) {
+                           const int p = i % PB;
+                           if (p < np) col[(int64_t)(i / PB) * nq + p] = v;
+                         });
+}
+
 // ------------------------------------------------------------------ pass I
 // Backward C2C along y and C2R along x of one interior z-plane of one of the 6
 // output fields; writes the interior cells of the plane, scaled by 1/V.
@@ -403,7 +472,7 @@ struct InvArgs {
 
 // LDS: the plane with row stride ld, then the twiddles of the y plan (Py),
 // the x plan (Nh) and W_Px.
-template <typename T, bool INC, int MAXR, class Bar, class Eng = FftValu>
+template <typename T, bool INC, int MAXR, bool PUSH = false, class Bar, class Eng = FftValu>
 PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar, Eng eng = Eng{}) {
   const int s = find_box(a.items, a.t.nsub, item);
   const BoxD& bx = a.t.box[s];
@@ -466,8 +535,8 @@ PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>*
   const int nx = bx.n[0], gx = bx.g[0];
   T* dst = a.out[f] + bx.foff + (int64_t)z * Py * Px;
   const FastDiv dnx = make_fastdiv((uint32_t)nx);
-  T* ldsT = reinterpret_cast<T*>(lds);
-  const bool push = a.push_off != nullptr;
+  [[maybe_unused]] T* ldsT = reinterpret_cast<T*>(lds);
+  constexpr bool push = PUSH;  // the fused E,B exchange (compiled only where used)
   copy_batched<8, T>(ny * nx, tid, nt,
                      [&](int i) {
                        const int yy = (int)fdiv((uint32_t)i, dnx);
@@ -482,9 +551,9 @@ PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>*
                        const T nv = INC ? *q + v : v;  // INC: v is the increment
                        *q = nv;
                        // the new value back into its own LDS slot for the guard copies
-                       if (push) ldsT[2 * ((gy + yy) * ld + posx[x >> 1]) + (x & 1)] = nv;
+                       if constexpr (push) ldsT[2 * ((gy + yy) * ld + posx[x >> 1]) + (x & 1)] = nv;
                      });
-  if (push) {
+  if constexpr (push) {
     bar();
     push_guards<T>(a.push, a.push_off[s], a.push_off[s + 1], a.t.box, a.out[f], z - bx.g[2], 0, ny,
                    [&](int yi, int xi) {
@@ -630,7 +699,7 @@ PSATD_HD void body_y(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>* ld
 
 // x inverse: kRB interior rows of (box, interior z, output field):
 // half spectrum rows -> real rows, interior cells written (INC: added).
-template <typename T, bool INC, int MAXR, class Bar, class Eng = FftValu>
+template <typename T, bool INC, int MAXR, bool PUSH = false, class Bar, class Eng = FftValu>
 PSATD_HD void body_x_inv(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>* lds, Bar bar, Eng eng = Eng{}) {
   const int s = find_box(a.items, a.t.nsub, item);
   const BoxD& bx = a.t.box[s];
@@ -683,8 +752,8 @@ PSATD_HD void body_x_inv(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>
   const int nx = bx.n[0], gx = bx.g[0];
   T* dst = a.out[f] + bx.foff + ((int64_t)z * Py + y0) * Px;
   const FastDiv dnx = make_fastdiv((uint32_t)nx);
-  T* ldsT = reinterpret_cast<T*>(lds);
-  const bool push = a.push_off != nullptr;
+  [[maybe_unused]] T* ldsT = reinterpret_cast<T*>(lds);
+  constexpr bool push = PUSH;  // the fused E,B exchange (compiled only where used)
   copy_batched<8, T>(ny * nx, tid, nt,
                      [&](int i) {
                        const int y = (int)fdiv((uint32_t)i, dnx);
@@ -698,9 +767,9 @@ PSATD_HD void body_x_inv(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>
                        T* q = dst + y * Px + x;
                        const T nv = INC ? *q + v : v;
                        *q = nv;
-                       if (push) ldsT[2 * (y * ld + posx[x >> 1]) + (x & 1)] = nv;
+                       if constexpr (push) ldsT[2 * (y * ld + posx[x >> 1]) + (x & 1)] = nv;
                      });
-  if (push) {
+  if constexpr (push) {
     bar();
     push_guards<T>(a.push, a.push_off[s], a.push_off[s + 1], a.t.box, a.out[f], zz, yy0, yy0 + ny,
                    [&](int yi, int xi) {

@@ -59,12 +59,12 @@ __global__ __launch_bounds__(NT) void k_fwd_xy(FwdArgs<T> a, int item0, int nite
   }
 }
 
-template <typename T, bool INC, int NT, int MAXR, int SPL>
+template <typename T, bool INC, int NT, int MAXR, int SPL, bool PUSH>
 __global__ __launch_bounds__(NT) void k_inv_xy(InvArgs<T> a, int item0, int nitems, int remap) {
   cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
   for (int it = first_item(remap); it < nitems; it += gridDim.x) {
-    body_inv_xy<T, INC, MAXR>(a, item0 + it, threadIdx.x, NT, lds, BlockBarrier{},
-                              typename EngOf<SPL>::type{});
+    body_inv_xy<T, INC, MAXR, PUSH>(a, item0 + it, threadIdx.x, NT, lds, BlockBarrier{},
+                                    typename EngOf<SPL>::type{});
     __syncthreads();
   }
 }
@@ -75,6 +75,16 @@ __global__ __launch_bounds__(NT) void k_z_update(UpdArgs<T> a, int item0, int ni
   for (int it = first_item(remap); it < nitems; it += gridDim.x) {
     body_z_update<T, PB, INC, MAXR>(a, item0 + it, threadIdx.x, NT, lds, BlockBarrier{},
                                     typename EngOf<SPL>::type{});
+    __syncthreads();
+  }
+}
+
+template <typename T, int PB, bool INC, int MAXR, int SPL>
+__global__ __launch_bounds__(kThreadsXY) void k_z_heat(HeatArgs<T> a, int nitems, int remap) {
+  cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
+  for (int it = first_item(remap); it < nitems; it += gridDim.x) {
+    body_z_heat<T, PB, INC, MAXR>(a, it, threadIdx.x, kThreadsXY, lds, BlockBarrier{},
+                                  typename EngOf<SPL>::type{});
     __syncthreads();
   }
 }
@@ -97,12 +107,12 @@ __global__ __launch_bounds__(kThreadsXY) void k_y(SplitArgs<T> a, int nitems, in
   }
 }
 
-template <typename T, bool INC, int MAXR, int SPL>
+template <typename T, bool INC, int MAXR, int SPL, bool PUSH>
 __global__ __launch_bounds__(kThreadsXY) void k_x_inv(SplitArgs<T> a, int nitems, int remap) {
   cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
   for (int it = first_item(remap); it < nitems; it += gridDim.x) {
-    body_x_inv<T, INC, MAXR>(a, it, threadIdx.x, kThreadsXY, lds, BlockBarrier{},
-                             typename EngOf<SPL>::type{});
+    body_x_inv<T, INC, MAXR, PUSH>(a, it, threadIdx.x, kThreadsXY, lds, BlockBarrier{},
+                                   typename EngOf<SPL>::type{});
     __syncthreads();
   }
 }
@@ -179,7 +189,10 @@ template <typename T, int MAXR, int SPL>
 static hipError_t prepare_t(int ldsF, int ldsI, int ldsU, int ldsX, int ldsY) {
   constexpr bool I = IncOf<T>::value;
   const void* xy[] = {(const void*)k_fwd_xy<T, 256, MAXR, SPL>, (const void*)k_fwd_xy<T, 512, MAXR, SPL>};
-  const void* inv[] = {(const void*)k_inv_xy<T, I, 256, MAXR, SPL>, (const void*)k_inv_xy<T, I, 512, MAXR, SPL>};
+  const void* inv[] = {(const void*)k_inv_xy<T, I, 256, MAXR, SPL, false>,
+                       (const void*)k_inv_xy<T, I, 512, MAXR, SPL, false>,
+                       (const void*)k_inv_xy<T, I, 256, MAXR, SPL, true>,
+                       (const void*)k_inv_xy<T, I, 512, MAXR, SPL, true>};
   const void* upd[] = {(const void*)k_z_update<T, 512, 8, I, MAXR, SPL>,
                        (const void*)k_z_update<T, 512, 16, I, MAXR, SPL>,
                        (const void*)k_z_update<T, 1024, 8, I, MAXR, SPL>,
@@ -192,8 +205,13 @@ static hipError_t prepare_t(int ldsF, int ldsI, int ldsU, int ldsX, int ldsY) {
     if (ldsI <= kMaxDynLds && (e = set_lds(f, ldsI)) != hipSuccess) return e;
   for (const void* f : upd)
     if ((e = set_lds(f, ldsU)) != hipSuccess) return e;
+  const void* heat[] = {(const void*)k_z_heat<T, 4, I, MAXR, SPL>, (const void*)k_z_heat<T, 8, I, MAXR, SPL>,
+                        (const void*)k_z_heat<T, 16, I, MAXR, SPL>};
+  for (const void* f : heat)
+    if ((e = set_lds(f, ldsU)) != hipSuccess) return e;
   if ((e = set_lds((const void*)k_x_fwd<T, MAXR, SPL>, ldsX)) != hipSuccess) return e;
-  if ((e = set_lds((const void*)k_x_inv<T, I, MAXR, SPL>, ldsX)) != hipSuccess) return e;
+  if ((e = set_lds((const void*)k_x_inv<T, I, MAXR, SPL, false>, ldsX)) != hipSuccess) return e;
+  if ((e = set_lds((const void*)k_x_inv<T, I, MAXR, SPL, true>, ldsX)) != hipSuccess) return e;
   if ((e = set_lds((const void*)k_y<T, -1, MAXR, SPL>, ldsY)) != hipSuccess) return e;
   return set_lds((const void*)k_y<T, 1, MAXR, SPL>, ldsY);
 }
@@ -269,12 +287,13 @@ static hipError_t fwd_go(const DevPlan& p, const Batch& b, const FwdArgs<T>& a, 
 }
 
 template <typename T>
-static hipError_t fwd_t(const DevPlan& p, const Batch& b, void* const* in9, void* spec, hipStream_t st) {
+static hipError_t fwd_t(const DevPlan& p, const Batch& b, void* const* in9, void* spec, hipStream_t st,
+                        bool scalar) {
   FwdArgs<T> a;
   a.t = tables<T>(p);
-  a.items = p.itemsF;
-  a.nfield = 9;
-  for (int f = 0; f < 9; ++f) a.in[f] = reinterpret_cast<const T*>(in9[f]);
+  a.items = scalar ? p.itemsP : p.itemsF;  // one field: P[2] planes per box
+  a.nfield = scalar ? 1 : 9;
+  for (int f = 0; f < 9; ++f) a.in[f] = (f < a.nfield) ? reinterpret_cast<const T*>(in9[f]) : nullptr;
   a.spec = reinterpret_cast<cx<T>*>(spec);
   a.slab = p.slab;
   a.sbias = b.sbias;
@@ -291,8 +310,9 @@ static hipError_t fwd_t(const DevPlan& p, const Batch& b, void* const* in9, void
   });
 }
 
-hipError_t launch_fwd(const DevPlan& p, const Batch& b, void* const* in9, void* spec, hipStream_t st) {
-  return p.f64 ? fwd_t<double>(p, b, in9, spec, st) : fwd_t<float>(p, b, in9, spec, st);
+hipError_t launch_fwd(const DevPlan& p, const Batch& b, void* const* in9, void* spec, hipStream_t st,
+                      bool scalar) {
+  return p.f64 ? fwd_t<double>(p, b, in9, spec, st, scalar) : fwd_t<float>(p, b, in9, spec, st, scalar);
 }
 
 template <typename T, int NT, int PB, int MAXR, int SPL>
@@ -338,22 +358,27 @@ hipError_t launch_upd(const DevPlan& p, const Batch& b, void* spec, hipStream_t 
 
 template <typename T, int NT, int MAXR, int SPL>
 static hipError_t inv_go(const DevPlan& p, const Batch& b, const InvArgs<T>& a, int g, hipStream_t st) {
-  hipLaunchKernelGGL((k_inv_xy<T, IncOf<T>::value, NT, MAXR, SPL>), dim3(g), dim3(NT), p.ldsI, st, a, b.I0,
-                     b.nI, p.xcd);
+  if (a.push_off)
+    hipLaunchKernelGGL((k_inv_xy<T, IncOf<T>::value, NT, MAXR, SPL, true>), dim3(g), dim3(NT), p.ldsI, st, a,
+                       b.I0, b.nI, p.xcd);
+  else
+    hipLaunchKernelGGL((k_inv_xy<T, IncOf<T>::value, NT, MAXR, SPL, false>), dim3(g), dim3(NT), p.ldsI, st, a,
+                       b.I0, b.nI, p.xcd);
   return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t inv_t(const DevPlan& p, const Batch& b, const void* spec, void* const* out6, hipStream_t st) {
+static hipError_t inv_t(const DevPlan& p, const Batch& b, const void* spec, void* const* out6, hipStream_t st,
+                        bool scalar) {
   InvArgs<T> a;
   a.t = tables<T>(p);
-  a.items = p.itemsI;
+  a.items = scalar ? p.itemsN : p.itemsI;  // one field: n[2] planes per box
   a.spec = reinterpret_cast<const cx<T>*>(spec);
   a.slab = p.slab;
   a.sbias = b.sbias;
-  for (int f = 0; f < 6; ++f) a.out[f] = reinterpret_cast<T*>(out6[f]);
-  a.push = p.fuse ? p.push : nullptr;
-  a.push_off = p.fuse ? p.push_off : nullptr;
+  for (int f = 0; f < 6; ++f) a.out[f] = (f == 0 || !scalar) ? reinterpret_cast<T*>(out6[f]) : nullptr;
+  a.push = (p.fuse && !scalar) ? p.push : nullptr;
+  a.push_off = (p.fuse && !scalar) ? p.push_off : nullptr;
   const int g = grid_for(b.nI, p.grid_cap[kPhaseInv]);
   if (!g) return hipSuccess;
   return with_spl<T>(p.spl, [&](auto sc) -> hipError_t {
@@ -367,8 +392,41 @@ static hipError_t inv_t(const DevPlan& p, const Batch& b, const void* spec, void
   });
 }
 
-hipError_t launch_inv(const DevPlan& p, const Batch& b, const void* spec, void* const* out6, hipStream_t st) {
-  return p.f64 ? inv_t<double>(p, b, spec, out6, st) : inv_t<float>(p, b, spec, out6, st);
+hipError_t launch_inv(const DevPlan& p, const Batch& b, const void* spec, void* const* out6, hipStream_t st,
+                      bool scalar) {
+  return p.f64 ? inv_t<double>(p, b, spec, out6, st, scalar) : inv_t<float>(p, b, spec, out6, st, scalar);
+}
+
+template <typename T>
+static hipError_t heat_z_t(const DevPlan& p, void* spec, double D, double dt, hipStream_t st) {
+  HeatArgs<T> a;
+  a.t = tables<T>(p);
+  a.items = p.itemsU;
+  a.spec = reinterpret_cast<cx<T>*>(spec);
+  a.D = D;
+  a.dt = dt;
+  const int g = grid_for(p.nU, p.grid_cap[kPhaseUpd]);
+  if (!g) return hipSuccess;
+  constexpr bool I = IncOf<T>::value;
+  return with_spl<T>(p.spl, [&](auto sc) -> hipError_t {
+    constexpr int SPL = decltype(sc)::value;
+    auto go = [&](auto pbc) -> hipError_t {
+      constexpr int PB = decltype(pbc)::value;
+      PSATD_MAXR_SWITCH(SPL,
+                        hipLaunchKernelGGL((k_z_heat<T, PB, I, 8, SPL>), dim3(g), dim3(kThreadsXY), p.ldsH, st,
+                                           a, p.nU, p.xcd),
+                        hipLaunchKernelGGL((k_z_heat<T, PB, I, 16, SPL>), dim3(g), dim3(kThreadsXY), p.ldsH, st,
+                                           a, p.nU, p.xcd));
+      return hipGetLastError();
+    };
+    if (p.PB == 4) return go(std::integral_constant<int, 4>{});
+    if (p.PB == 8) return go(std::integral_constant<int, 8>{});
+    return go(std::integral_constant<int, 16>{});
+  });
+}
+
+hipError_t launch_heat_z(const DevPlan& p, void* spec, double D, double dt, hipStream_t st) {
+  return p.f64 ? heat_z_t<double>(p, spec, D, dt, st) : heat_z_t<float>(p, spec, D, dt, st);
 }
 
 template <typename T>
@@ -439,11 +497,16 @@ static hipError_t x_inv_t(const DevPlan& p, const void* spec, void* const* out6,
   constexpr bool I = IncOf<T>::value;
   return with_spl<T>(p.spl, [&](auto sc) -> hipError_t {
     constexpr int SPL = decltype(sc)::value;
-    PSATD_MAXR_SWITCH(SPL,
-                      hipLaunchKernelGGL((k_x_inv<T, I, 8, SPL>), dim3(g), dim3(kThreadsXY), p.ldsX, st, a,
-                                         p.nXI, p.xcd),
-                      hipLaunchKernelGGL((k_x_inv<T, I, 16, SPL>), dim3(g), dim3(kThreadsXY), p.ldsX, st, a,
-                                         p.nXI, p.xcd));
+    auto go = [&](auto pc) {
+      constexpr bool PUSH = decltype(pc)::value;
+      PSATD_MAXR_SWITCH(SPL,
+                        hipLaunchKernelGGL((k_x_inv<T, I, 8, SPL, PUSH>), dim3(g), dim3(kThreadsXY), p.ldsX, st,
+                                           a, p.nXI, p.xcd),
+                        hipLaunchKernelGGL((k_x_inv<T, I, 16, SPL, PUSH>), dim3(g), dim3(kThreadsXY), p.ldsX, st,
+                                           a, p.nXI, p.xcd));
+    };
+    if (a.push_off) go(std::true_type{});
+    else go(std::false_type{});
     return hipGetLastError();
   });
 }

@@ -38,6 +38,7 @@ struct DevPlan {
   int32_t spl;               // BF16 terms of the matrix-core DFT stage (0: VALU only)
   int32_t nF, nU, nI, nP, nN;
   int32_t ldsF, ldsI, ldsU;  // dynamic LDS bytes per work-group
+  int32_t ldsH;              // heat z pass: one staged field
   int32_t PB;                // pencils per z-update work-group
   int32_t ntu;               // threads per z-update work-group (512 or 1024)
   int32_t ntxy;              // threads per x/y work-group (256 or 512)
@@ -50,9 +51,13 @@ struct DevPlan {
 
 hipError_t launch_fill(const DevPlan& p, void* const* comps, int ncomp, hipStream_t st);
 hipError_t launch_sum(const DevPlan& p, void* const* J, hipStream_t st);
-hipError_t launch_fwd(const DevPlan& p, const Batch& b, void* const* in9, void* spec, hipStream_t st);
+hipError_t launch_fwd(const DevPlan& p, const Batch& b, void* const* in9, void* spec, hipStream_t st,
+                      bool scalar = false);
 hipError_t launch_upd(const DevPlan& p, const Batch& b, void* spec, hipStream_t st);
-hipError_t launch_inv(const DevPlan& p, const Batch& b, const void* spec, void* const* out6, hipStream_t st);
+hipError_t launch_inv(const DevPlan& p, const Batch& b, const void* spec, void* const* out6, hipStream_t st,
+                      bool scalar = false);
+// heat equation (Sec. 5): z pass of one field with the exp(-D |[k]|^2 dt) propagator
+hipError_t launch_heat_z(const DevPlan& p, void* spec, double D, double dt, hipStream_t st);
 // split x/y passes (whole plan, no batching)
 hipError_t launch_x_fwd(const DevPlan& p, void* const* in9, void* spec, hipStream_t st);
 hipError_t launch_y(const DevPlan& p, int dir, void* spec, hipStream_t st);

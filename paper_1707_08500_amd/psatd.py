@@ -32,7 +32,7 @@ STATUS = {0: "PSATD_OK", 1: "PSATD_E_INVALID", 2: "PSATD_E_NOMEM", 3: "PSATD_E_H
           4: "PSATD_E_UNSUPPORTED", 5: "PSATD_E_STATE"}
 
 SYMBOLS = ("psatd_plan", "psatd_validate", "psatd_field_elems", "psatd_field_layout",
-           "psatd_workspace_bytes", "psatd_set_workspace", "psatd_step", "psatd_run",
+           "psatd_workspace_bytes", "psatd_set_workspace", "psatd_step", "psatd_run", "psatd_heat_run",
            "psatd_run_profiled", "psatd_scatter", "psatd_gather", "psatd_modified_k",
            "psatd_set_tuning", "psatd_get_tuning", "psatd_autotune", "psatd_set_stream", "psatd_sync", "psatd_destroy", "psatd_status_string",
            "psatd_last_error", "psatd_version")
@@ -64,6 +64,7 @@ def _load():
         "psatd_step": ([P, VPP, VPP, VPP], i32),
         "psatd_run": ([P, VPP, VPP, VPP, i32], i32),
         "psatd_run_profiled": ([P, VPP, VPP, VPP, i32, DP], i32),
+        "psatd_heat_run": ([P, P, f64, i32], i32),
         "psatd_scatter": ([P, VPP, VPP], i32),
         "psatd_gather": ([P, VPP, VPP], i32),
         "psatd_modified_k": ([P, i32, i32, DP, i64], i32),
@@ -180,6 +181,11 @@ class Plan:
 
     def run(self, E, B, J, nsteps):
         _check(LIB.psatd_run(self._h, _ptrs(E), _ptrs(B), _ptrs(J), int(nsteps)), self._h)
+
+    def heat_run(self, u, diffusivity, nsteps):
+        """psatd_heat_run: nsteps heat-equation steps of one padded field buffer."""
+        _check(LIB.psatd_heat_run(self._h, ctypes.c_void_p(u.data_ptr()), float(diffusivity),
+                                  int(nsteps)), self._h)
 
     def run_profiled(self, E, B, J, nsteps):
         out = (ctypes.c_double * NPHASES)()
