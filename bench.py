@@ -289,7 +289,7 @@ def main():
               end="")
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
               f"(the single-GPU kernel is the per-GPU share of a sharded run)", file=sys.stderr)
         sys.exit(2)
 
