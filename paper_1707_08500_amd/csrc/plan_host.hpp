@@ -38,6 +38,8 @@ struct HostTables {
   bool split = false;  // x/y pass split into x rows and y columns (large planes)
   std::vector<PushBlk> push;      // fused E,B exchange: guard pieces per source box
   std::vector<int32_t> push_off;  // nsub + 1
+  std::vector<int32_t> itemsG;    // guard fill: prefix over pieces of their z extent
+  std::vector<int32_t> pieceOf;   // guard fill: item -> piece
   bool fuse_eb = false;           // E,B guards written by the inverse pass
   int ldsX = 0, ldsY = 0;
   std::vector<Batch> batches;
@@ -301,11 +303,17 @@ inline void build_push(HostTables& h) {
             const bool own = d == s && z.q0 == b.g[2] && y.q0 == b.g[1] && x.q0 == b.g[0] &&
                              z.i0 == 0 && y.i0 == 0 && x.i0 == 0;
             if (own) continue;  // the interior itself
-            h.push.push_back({d, z.i0, z.len, z.q0, y.i0, y.len, y.q0, x.i0, x.len, x.q0});
+            h.push.push_back({s, d, z.i0, z.len, z.q0, y.i0, y.len, y.q0, x.i0, x.len, x.q0});
           }
     }
     h.push_off[s + 1] = (int32_t)h.push.size();
   }
+  // work list of the guard fill: one item per z-plane of every piece
+  h.itemsG.assign(h.push.size() + 1, 0);
+  for (size_t b = 0; b < h.push.size(); ++b) h.itemsG[b + 1] = h.itemsG[b] + h.push[b].lz;
+  h.pieceOf.resize(h.itemsG.back());
+  for (size_t b = 0; b < h.push.size(); ++b)
+    for (int32_t i = h.itemsG[b]; i < h.itemsG[b + 1]; ++i) h.pieceOf[i] = (int32_t)b;
 }
 
 // Does the circular interval [a, a+len) (len < N) meet [lo, lo+n) on Z_N?

@@ -254,9 +254,6 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   const size_t o_tw = reserve(h.twr.size() * cs);
   const size_t o_kmod = reserve((size_t)h.kmod_len * 8);
   const size_t o_kent = reserve(h.kent.size() * sizeof(KEntry));
-  size_t o_cut[3];
-  for (int u = 0; u < 3; ++u) o_cut[u] = reserve(h.cut[u].size() * 4);
-  const size_t o_own = reserve(h.owner.size() * 4);
   const size_t o_nbo = reserve(h.nbr_off.size() * 4);
   const size_t o_nbr = reserve(std::max<size_t>(h.nbr.size(), 1) * 4);
   const size_t o_iF = reserve(h.itemsF.size() * 4);
@@ -269,6 +266,8 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   const size_t o_iXI = reserve(h.itemsXI.size() * 4);
   const size_t o_push = reserve(std::max<size_t>(h.push.size(), 1) * sizeof(PushBlk));
   const size_t o_pof = reserve(h.push_off.size() * 4);
+  const size_t o_iG = reserve(h.itemsG.size() * 4);
+  const size_t o_pOf = reserve(std::max<size_t>(h.pieceOf.size(), 1) * 4);
   std::vector<unsigned char> hb(total, 0);
   auto put = [&](size_t off, const void* src, size_t bytes) {
     if (bytes) std::memcpy(hb.data() + off, src, bytes);
@@ -285,8 +284,6 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
     put(o_tw, t.data(), t.size() * sizeof(cx<float>));
   }
   put(o_kent, h.kent.data(), h.kent.size() * sizeof(KEntry));
-  for (int u = 0; u < 3; ++u) put(o_cut[u], h.cut[u].data(), h.cut[u].size() * 4);
-  put(o_own, h.owner.data(), h.owner.size() * 4);
   put(o_nbo, h.nbr_off.data(), h.nbr_off.size() * 4);
   put(o_nbr, h.nbr.data(), h.nbr.size() * 4);
   put(o_iF, h.itemsF.data(), h.itemsF.size() * 4);
@@ -299,6 +296,8 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   put(o_iXI, h.itemsXI.data(), h.itemsXI.size() * 4);
   put(o_push, h.push.data(), h.push.size() * sizeof(PushBlk));
   put(o_pof, h.push_off.data(), h.push_off.size() * 4);
+  put(o_iG, h.itemsG.data(), h.itemsG.size() * 4);
+  put(o_pOf, h.pieceOf.data(), h.pieceOf.size() * 4);
   if ((e = hipMalloc(&p->blob, total)) != hipSuccess) return hipfail(e, "hipMalloc(tables)");
   if ((e = hipMemcpy(p->blob, hb.data(), total, hipMemcpyHostToDevice)) != hipSuccess)
     return hipfail(e, "hipMemcpy(tables)");
@@ -328,12 +327,6 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   d.plans = reinterpret_cast<const FftPlanD*>(B + o_plan);
   d.tw = B + o_tw;
   d.kmod = reinterpret_cast<const double*>(B + o_kmod);
-  for (int u = 0; u < 3; ++u) {
-    d.own.cut[u] = reinterpret_cast<const int32_t*>(B + o_cut[u]);
-    d.own.ncut[u] = h.ncut[u];
-    d.own.N[u] = (int32_t)h.N[u];
-  }
-  d.own.owner = reinterpret_cast<const int32_t*>(B + o_own);
   d.nbr_off = reinterpret_cast<const int32_t*>(B + o_nbo);
   d.nbr = reinterpret_cast<const int32_t*>(B + o_nbr);
   d.itemsF = reinterpret_cast<const int32_t*>(B + o_iF);
@@ -354,6 +347,10 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   d.split = h.split ? 1 : 0;
   d.push = reinterpret_cast<const PushBlk*>(B + o_push);
   d.push_off = reinterpret_cast<const int32_t*>(B + o_pof);
+  d.itemsG = reinterpret_cast<const int32_t*>(B + o_iG);
+  d.pieceOf = reinterpret_cast<const int32_t*>(B + o_pOf);
+  d.npiece = (int32_t)h.push.size();
+  d.nG = h.itemsG.back();
   d.fuse = (h.fuse_eb && h.batches.size() == 1) ? 1 : 0;
   d.spl = h.spl;
   p->tune[PSATD_TUNE_FUSE_EB] = d.fuse;

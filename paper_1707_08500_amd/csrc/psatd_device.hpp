@@ -48,7 +48,7 @@ struct Batch {
 // box are the padded cells starting at (qz, qy, qx) of box dst.  Every guard
 // cell of every box lies in exactly one piece of exactly one source box.
 struct PushBlk {
-  int32_t dst;
+  int32_t src, dst;
   int32_t z0, lz, qz;
   int32_t y0, ly, qy;
   int32_t x0, lx, qx;
@@ -781,73 +781,76 @@ PSATD_HD void body_x_inv(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>
 }
 
 // --------------------------------------------------------------- exchange
-// Owner lookup for a global cell: per-axis cut index (tensor refinement of
-// every box boundary), then a table over the refined cells.
-struct OwnerD {
-  const int32_t* cut[3];   // global index -> refined interval, per axis
-  int32_t ncut[3];
-  const int32_t* owner;    // [cz][cy][cx] -> box
-  int32_t N[3];
-};
-
-PSATD_HD int owner_of(const OwnerD& o, int X, int Y, int Z) {
-  return o.owner[(o.cut[2][Z] * o.ncut[1] + o.cut[1][Y]) * o.ncut[0] + o.cut[0][X]];
-}
 
 template <typename T>
 struct FillArgs {
   const BoxD* box;
-  int32_t nsub;
-  const int32_t* items;  // prefix over boxes of P[2]
-  OwnerD own;
+  const PushBlk* piece;     // guard pieces (each guard cell in exactly one)
+  const int32_t* items;     // prefix over pieces of lz
+  const int32_t* piece_of;  // item -> piece
   int32_t ncomp;
   T* comp[9];
 };
 
-// Fig. 3 step 3: every guard cell of box s takes the value of the owner of
-// its global index (mod N).  One padded z-plane per item.
+// 16 bytes of T, copied as one vector access.
+template <typename T>
+struct alignas(16) Vec16 {
+  T v[16 / sizeof(T)];
+};
+
+// Fig. 3 step 3: every guard cell takes the value of the owner of its global
+// index (mod N).  One item = one z-plane of one guard piece: ly rows of lx
+// cells, contiguous in the owner's interior and in the destination's guard
+// region, copied for every component (16-byte accesses when rows and bases
+// are 16-byte aligned).
 template <typename T>
 PSATD_HD void body_fill(const FillArgs<T>& a, int item, int tid, int nt) {
-  const int s = find_box(a.items, a.nsub, item);
-  const BoxD& bx = a.box[s];
-  const int z = item - a.items[s];
-  const int Px = bx.P[0], Py = bx.P[1];
-  const bool zg = z < bx.g[2] || z >= bx.g[2] + bx.n[2];
-  const int Z = pmod(bx.lo[2] - bx.g[2] + z, a.own.N[2]);
-  const int gx = bx.g[0], nx = bx.n[0];
-  const int64_t rowbase = bx.foff + (int64_t)z * Py * Px;
-  constexpr int U = 4;
-  for (int base = tid; base < Py * Px; base += U * nt) {
-    int64_t src[U], dst[U];
-    bool ok[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = base + u * nt;
-      ok[u] = false;
-      src[u] = dst[u] = 0;
-      if (i >= Py * Px) continue;
-      const int y = i / Px;
-      const int x = i - y * Px;
-      const bool yg = y < bx.g[1] || y >= bx.g[1] + bx.n[1];
-      const bool xg = x < gx || x >= gx + nx;
-      if (!(zg || yg || xg)) continue;  // interior cells are not touched
-      const int Y = pmod(bx.lo[1] - bx.g[1] + y, a.own.N[1]);
-      const int X = pmod(bx.lo[0] - gx + x, a.own.N[0]);
-      const BoxD& bo = a.box[owner_of(a.own, X, Y, Z)];
-      src[u] = bo.foff + ((int64_t)(Z - bo.lo[2] + bo.g[2]) * bo.P[1] + (Y - bo.lo[1] + bo.g[1])) * bo.P[0] +
-               (X - bo.lo[0] + bo.g[0]);
-      dst[u] = rowbase + i;
-      ok[u] = true;
-    }
-    for (int c = 0; c < a.ncomp; ++c) {
-      T v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (ok[u]) v[u] = a.comp[c][src[u]];
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (ok[u]) a.comp[c][dst[u]] = v[u];
-    }
+  const int b = a.piece_of[item];
+  const PushBlk k = a.piece[b];
+  const int zi = item - a.items[b];
+  const BoxD& sb = a.box[k.src];
+  const BoxD& db = a.box[k.dst];
+  const int sP0 = sb.P[0], dP0 = db.P[0];
+  const int64_t so = sb.foff + ((int64_t)(sb.g[2] + k.z0 + zi) * sb.P[1] + (sb.g[1] + k.y0)) * sP0 +
+                     sb.g[0] + k.x0;
+  const int64_t dof = db.foff + ((int64_t)(k.qz + zi) * db.P[1] + k.qy) * dP0 + k.qx;
+  constexpr int V = 16 / (int)sizeof(T);
+  const bool vec = (k.lx % V) == 0 && (so % V) == 0 && (dof % V) == 0 && (sP0 % V) == 0 && (dP0 % V) == 0;
+  const int W = vec ? V : 1;  // elements per access
+  const int lw = k.lx / W;
+  const int n = k.ly * lw;
+  const FastDiv dn = make_fastdiv((uint32_t)n);
+  const FastDiv dl = make_fastdiv((uint32_t)lw);
+  auto at = [&](int i, int64_t base, int pitch, int& c) {
+    c = (int)fdiv((uint32_t)i, dn);
+    const int e = i - c * n;
+    const int r = (int)fdiv((uint32_t)e, dl);
+    return base + (int64_t)r * pitch + (int64_t)(e - r * lw) * W;
+  };
+  if (vec) {
+    copy_batched<4, Vec16<T>>(n * a.ncomp, tid, nt,
+        [&](int i) {
+          int c;
+          const int64_t o = at(i, so, sP0, c);
+          return *reinterpret_cast<const Vec16<T>*>(a.comp[c] + o);
+        },
+        [&](int i, Vec16<T> v) {
+          int c;
+          const int64_t o = at(i, dof, dP0, c);
+          *reinterpret_cast<Vec16<T>*>(a.comp[c] + o) = v;
+        });
+  } else {
+    copy_batched<8, T>(n * a.ncomp, tid, nt,
+        [&](int i) {
+          int c;
+          const int64_t o = at(i, so, sP0, c);  // sets c before the buffer is chosen
+          return a.comp[c][o];
+        },
+        [&](int i, T v) {
+          int c;
+          const int64_t o = at(i, dof, dP0, c);
+          a.comp[c][o] = v;
+        });
   }
 }
 

@@ -233,14 +233,14 @@ template <typename T>
 static hipError_t fill_t(const DevPlan& p, void* const* comps, int ncomp, hipStream_t st) {
   FillArgs<T> a;
   a.box = p.box;
-  a.nsub = p.nsub;
-  a.items = p.itemsP;
-  a.own = p.own;
+  a.piece = p.push;
+  a.items = p.itemsG;
+  a.piece_of = p.pieceOf;
   a.ncomp = ncomp;
   for (int c = 0; c < 9; ++c) a.comp[c] = (c < ncomp) ? reinterpret_cast<T*>(comps[c]) : nullptr;
-  const int g = grid_for(p.nP, p.grid_cap[kPhaseExchEB]);
+  const int g = grid_for(p.nG, p.grid_cap[kPhaseExchEB]);
   if (!g) return hipSuccess;
-  hipLaunchKernelGGL(k_fill<T>, dim3(g), dim3(kThreadsXY), 0, st, a, p.nP, p.xcd);
+  hipLaunchKernelGGL(k_fill<T>, dim3(g), dim3(kThreadsXY), 0, st, a, p.nG, p.xcd);
   return hipGetLastError();
 }
 

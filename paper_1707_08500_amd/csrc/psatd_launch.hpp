@@ -17,7 +17,6 @@ struct DevPlan {
   const FftPlanD* plans;
   const void* tw;           // cx<double> or cx<float> twiddles
   const double* kmod;
-  OwnerD own;
   const int32_t* nbr_off;
   const int32_t* nbr;
   const int32_t* itemsF;    // P[2] * 9
@@ -32,7 +31,10 @@ struct DevPlan {
   int32_t nXF, nYF, nYI, nXI;
   int32_t ldsX, ldsY;
   int32_t split;
-  const PushBlk* push;       // guard pieces of the fused E,B exchange
+  const PushBlk* push;       // guard pieces (guard fill, fused E,B exchange)
+  const int32_t* itemsG;     // guard fill: prefix over pieces of their z extent
+  const int32_t* pieceOf;    // guard fill: item -> piece
+  int32_t npiece, nG;
   const int32_t* push_off;
   int32_t fuse;              // 1: the inverse pass writes the E,B guard copies
   int32_t spl;               // BF16 terms of the matrix-core DFT stage (0: VALU only)
