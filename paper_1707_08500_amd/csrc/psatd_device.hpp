@@ -98,6 +98,94 @@ PSATD_HD void copy_batched(int total, int tid, int nt, Src src, Dst dst) {
   }
 }
 
+// Row-major R x C walk shared by a work-group: element i = tid + k nt, with
+// its (row, col) advanced incrementally (no per-element division); full
+// batches of U run without bounds checks.  get(i, r, c) -> V, put(i, r, c, v).
+template <int U, class V, class Get, class Put>
+PSATD_HD void copy_grid(int R, int C, int tid, int nt, Get get, Put put) {
+  const int total = R * C;
+  const FastDiv dC = make_fastdiv((uint32_t)C);
+  int r = (int)fdiv((uint32_t)tid, dC);
+  int c = tid - r * C;
+  const int dr = (int)fdiv((uint32_t)nt, dC);
+  const int dc = nt - dr * C;
+  auto advance = [&](int& rr, int& cc) {
+    cc += dc;
+    rr += dr;
+    if (cc >= C) {
+      cc -= C;
+      ++rr;
+    }
+  };
+  int i = tid;
+  for (; i + (U - 1) * nt < total; i += U * nt) {
+    V v[U];
+    int rs[U], cs[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      rs[u] = r;
+      cs[u] = c;
+      v[u] = get(i + u * nt, r, c);
+      advance(r, c);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) put(i + u * nt, rs[u], cs[u], v[u]);
+  }
+  for (; i < total; i += nt) {
+    put(i, r, c, get(i, r, c));
+    advance(r, c);
+  }
+}
+
+// The same walk over an A x B x C box (C fastest): get(i, a, b, c), put(i, a, b, c, v).
+template <int U, class V, class Get, class Put>
+PSATD_HD void copy_grid3(int A, int B, int C, int tid, int nt, Get get, Put put) {
+  const int total = A * B * C;
+  const FastDiv dC = make_fastdiv((uint32_t)C);
+  const FastDiv dB = make_fastdiv((uint32_t)B);
+  auto split = [&](int v, int& a, int& b, int& c) {
+    const int q = (int)fdiv((uint32_t)v, dC);
+    c = v - q * C;
+    a = (int)fdiv((uint32_t)q, dB);
+    b = q - a * B;
+  };
+  int a, b, c, da, db, dc;
+  split(tid, a, b, c);
+  split(nt, da, db, dc);
+  auto advance = [&](int& aa, int& bb, int& cc) {
+    cc += dc;
+    bb += db;
+    aa += da;
+    if (cc >= C) {
+      cc -= C;
+      ++bb;
+    }
+    if (bb >= B) {
+      bb -= B;
+      ++aa;
+    }
+  };
+  int i = tid;
+  for (; i + (U - 1) * nt < total; i += U * nt) {
+    V v[U];
+    int as[U], bs[U], cs[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      as[u] = a;
+      bs[u] = b;
+      cs[u] = c;
+      v[u] = get(i + u * nt, a, b, c);
+      advance(a, b, c);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) put(i + u * nt, as[u], bs[u], cs[u], v[u]);
+  }
+  for (; i < total; i += nt) {
+    put(i, a, b, c, get(i, a, b, c));
+    advance(a, b, c);
+  }
+}
+
 // Fused E,B guard exchange: after the inverse pass of interior plane zi (rows
 // [ya, yb) of it held by this work-group), write the new values into every
 // guard copy of those cells.  val(y, x) returns the new value of interior cell
@@ -169,22 +257,10 @@ PSATD_HD void body_fwd_xy(const FwdArgs<T>& a, int item, int tid, int nt, cx<T>*
   // packed real rows (x natural) -> LDS rows in stage-digit order along x,
   // together with the three twiddle tables
   const cx<T>* src = reinterpret_cast<const cx<T>*>(a.in[f] + bx.foff + (int64_t)z * Py * Px);
-  const int nplane = Py * Nh;
-  const FastDiv dNh = make_fastdiv((uint32_t)Nh);
-  copy_batched<8, cx<T>>(nplane + Nh + Py + Px, tid, nt,
-                         [&](int i) {
-                           if (i < nplane) return src[i];
-                           const int j = i - nplane;
-                           return j < Nh ? gtx[j] : (j < Nh + Py ? gty[j - Nh] : gtr[j - Nh - Py]);
-                         },
-                         [&](int i, cx<T> v) {
-                           if (i < nplane) {
-                             const int y = (int)fdiv((uint32_t)i, dNh);
-                             lds[y * ld + posx[i - y * Nh]] = v;
-                           } else {
-                             twx[i - nplane] = v;  // twx, twy, twr are contiguous
-                           }
-                         });
+  for (int i = tid; i < Nh + Py + Px; i += nt)  // twx, twy, twr are contiguous
+    twx[i] = i < Nh ? gtx[i] : (i < Nh + Py ? gty[i - Nh] : gtr[i - Nh - Py]);
+  copy_grid<8, cx<T>>(Py, Nh, tid, nt, [&](int i, int, int) { return src[i]; },
+                      [&](int, int y, int x, cx<T> v) { lds[y * ld + posx[x]] = v; });
   bar();
   eng.template dit<-1, MAXR>(lds, Py, ld, 1, plx, twx, tid, nt, bar);
   const int np = Nh / 2 + 1;
@@ -196,13 +272,8 @@ PSATD_HD void body_fwd_xy(const FwdArgs<T>& a, int item, int tid, int nt, cx<T>*
   bar();
   eng.template dif<-1, MAXR>(lds, H, 1, ld, ply, twy, tid, nt, bar);
   cx<T>* dst = a.spec + f * a.slab + (bx.soff - a.sbias) + (int64_t)z * Py * H;
-  const FastDiv dH = make_fastdiv((uint32_t)H);
-  copy_batched<8, cx<T>>(Py * H, tid, nt,
-                         [&](int i) {
-                           const int ky = (int)fdiv((uint32_t)i, dH);
-                           return lds[posy[ky] * ld + (i - ky * H)];
-                         },
-                         [&](int i, cx<T> v) { dst[i] = v; });
+  copy_grid<8, cx<T>>(Py, H, tid, nt, [&](int, int ky, int kx) { return lds[posy[ky] * ld + kx]; },
+                      [&](int i, int, int, cx<T> v) { dst[i] = v; });
 }
 
 // ------------------------------------------------------------------ pass U
@@ -314,29 +385,12 @@ PSATD_HD void body_z_update(const UpdArgs<T>& a, int item, int tid, int nt, cx<T
   for (int i = tid; i < Pz; i += nt) kzi[i] = plan_index(plz, i);
   const cx<T>* src = a.spec + (bx.soff - a.sbias) + q0;
   const int64_t slab = a.slab;
-  const FastDiv dPz = make_fastdiv((uint32_t)Pz);
-  const int ndata = 9 * Pz * PB;
-
-  copy_batched<8, cx<T>>(ndata + Pz, tid, nt,
-      [&](int i) {
-        if (i >= ndata) return gtz[i - ndata];
-        const int p = i % PB;
-        const int r = i / PB;
-        const int f = (int)fdiv((uint32_t)r, dPz);
-        const int z = r - f * Pz;
+  for (int i = tid; i < Pz; i += nt) twz[i] = gtz[i];
+  copy_grid3<8, cx<T>>(9, Pz, PB, tid, nt,
+      [&](int, int f, int z, int p) {
         return (p < np) ? src[f * slab + (int64_t)z * nq + p] : cx<T>{T(0), T(0)};
       },
-      [&](int i, cx<T> v) {
-        if (i >= ndata) {
-          twz[i - ndata] = v;
-          return;
-        }
-        const int p = i % PB;
-        const int r = i / PB;
-        const int f = (int)fdiv((uint32_t)r, dPz);
-        const int z = r - f * Pz;
-        lds[z * W + f * PB + p] = v;
-      });
+      [&](int, int f, int z, int p, cx<T> v) { lds[z * W + f * PB + p] = v; });
   bar();
   eng.template dif<-1, MAXR>(lds, 9 * PB, 1, W, plz, twz, tid, nt, bar);
 
@@ -367,23 +421,10 @@ PSATD_HD void body_z_update(const UpdArgs<T>& a, int item, int tid, int nt, cx<T
   eng.template dit<+1, MAXR>(lds, 6 * PB, 1, W, plz, twz, tid, nt, bar);
 
   cx<T>* dst = a.spec + (bx.soff - a.sbias) + q0;
-  copy_batched<8, cx<T>>(6 * Pz * PB, tid, nt,
-      [&](int i) {
-        const int p = i % PB;
-        const int r = i / PB;
-        const int f = (int)fdiv((uint32_t)r, dPz);
-        const int z = r - f * Pz;
-        return lds[z * W + f * PB + p];
-      },
-      [&](int i, cx<T> v) {
-        const int p = i % PB;
-        if (p < np) {
-          const int r = i / PB;
-          const int f = (int)fdiv((uint32_t)r, dPz);
-          const int z = r - f * Pz;
-          dst[f * slab + (int64_t)z * nq + p] = v;
-        }
-      });
+  copy_grid3<8, cx<T>>(6, Pz, PB, tid, nt, [&](int, int f, int z, int p) { return lds[z * W + f * PB + p]; },
+                       [&](int, int f, int z, int p, cx<T> v) {
+                         if (p < np) dst[f * slab + (int64_t)z * nq + p] = v;
+                       });
 }
 
 // ------------------------------------------------------- heat equation
@@ -502,22 +543,10 @@ PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>*
 
   // half-spectrum rows (ky natural) -> LDS rows in stage-digit order along y
   const cx<T>* src = a.spec + f * a.slab + (bx.soff - a.sbias) + (int64_t)z * Py * H;
-  const int nplane = Py * H;
-  const FastDiv dH = make_fastdiv((uint32_t)H);
-  copy_batched<8, cx<T>>(nplane + Py + Nh + Px, tid, nt,
-                         [&](int i) {
-                           if (i < nplane) return src[i];
-                           const int j = i - nplane;
-                           return j < Py ? gty[j] : (j < Py + Nh ? gtx[j - Py] : gtr[j - Py - Nh]);
-                         },
-                         [&](int i, cx<T> v) {
-                           if (i < nplane) {
-                             const int ky = (int)fdiv((uint32_t)i, dH);
-                             lds[posy[ky] * ld + (i - ky * H)] = v;
-                           } else {
-                             twy[i - nplane] = v;  // twy, twx, twr are contiguous
-                           }
-                         });
+  for (int i = tid; i < Py + Nh + Px; i += nt)  // twy, twx, twr are contiguous
+    twy[i] = i < Py ? gty[i] : (i < Py + Nh ? gtx[i - Py] : gtr[i - Py - Nh]);
+  copy_grid<8, cx<T>>(Py, H, tid, nt, [&](int i, int, int) { return src[i]; },
+                      [&](int, int ky, int kx, cx<T> v) { lds[posy[ky] * ld + kx] = v; });
   bar();
   eng.template dit<+1, MAXR>(lds, H, 1, ld, ply, twy, tid, nt, bar);
   const int ny = bx.n[1], gy = bx.g[1];
@@ -534,25 +563,22 @@ PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>*
   const double sc = 1.0 / ((double)Px * (double)Py * (double)Pz);
   const int nx = bx.n[0], gx = bx.g[0];
   T* dst = a.out[f] + bx.foff + (int64_t)z * Py * Px;
-  const FastDiv dnx = make_fastdiv((uint32_t)nx);
   [[maybe_unused]] T* ldsT = reinterpret_cast<T*>(lds);
   constexpr bool push = PUSH;  // the fused E,B exchange (compiled only where used)
-  copy_batched<8, T>(ny * nx, tid, nt,
-                     [&](int i) {
-                       const int yy = (int)fdiv((uint32_t)i, dnx);
-                       const int x = gx + (i - yy * nx);
-                       const cx<T> v = lds[(gy + yy) * ld + posx[x >> 1]];
-                       return (T)((double)((x & 1) ? v.y : v.x) * sc);
-                     },
-                     [&](int i, T v) {
-                       const int yy = (int)fdiv((uint32_t)i, dnx);
-                       const int x = gx + (i - yy * nx);
-                       T* q = dst + (gy + yy) * Px + x;
-                       const T nv = INC ? *q + v : v;  // INC: v is the increment
-                       *q = nv;
-                       // the new value back into its own LDS slot for the guard copies
-                       if constexpr (push) ldsT[2 * ((gy + yy) * ld + posx[x >> 1]) + (x & 1)] = nv;
-                     });
+  copy_grid<8, T>(ny, nx, tid, nt,
+                  [&](int, int yy, int xi) {
+                    const int x = gx + xi;
+                    const cx<T> v = lds[(gy + yy) * ld + posx[x >> 1]];
+                    return (T)((double)((x & 1) ? v.y : v.x) * sc);
+                  },
+                  [&](int, int yy, int xi, T v) {
+                    const int x = gx + xi;
+                    T* q = dst + (gy + yy) * Px + x;
+                    const T nv = INC ? *q + v : v;  // INC: v is the increment
+                    *q = nv;
+                    // the new value back into its own LDS slot for the guard copies
+                    if constexpr (push) ldsT[2 * ((gy + yy) * ld + posx[x >> 1]) + (x & 1)] = nv;
+                  });
   if constexpr (push) {
     bar();
     push_guards<T>(a.push, a.push_off[s], a.push_off[s + 1], a.t.box, a.out[f], z - bx.g[2], 0, ny,
