@@ -37,6 +37,9 @@ WORKLOADS = {
     # name: grid, boxes per axis, guard, order p, dt
     "cfg2": dict(N=(256, 256, 256), nbox=(4, 4, 4), guard=16, p=32, dt=0.5,
                  desc="256^3 grid, 4x4x4 subdomains of 64^3, 16 guards (local FFT 96^3), p=32, dt=0.5, c=1"),
+    "cfg4": dict(N=(512, 512, 256), nbox=None, guard=None, p=64, dt=0.5,
+                 desc="512x512x256 grid cut into uneven subdomains (edges from {48,64,80,96}, guards from "
+                      "{8,16,32}), p=64, dt=0.5, c=1"),
     "cfg5": dict(N=(1024, 1024, 512), nbox=(8, 8, 4), guard=24, p=100, dt=0.5,
                  desc="1024x1024x512 grid, 8x8x4 subdomains of 128^3, 24 guards (local FFT 176^3), p=100, dt=0.5, c=1"),
 }
@@ -260,6 +263,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-global", action="store_true", help="skip the PSATD-global comparison leg")
+    ap.add_argument("--no-heat", action="store_true", help="skip the heat-equation leg")
     ap.add_argument("--precisions", default="f32,bf16x3,bf16x6",
                     help="FP32-state forms to time (comma list of f32, bf16x3, bf16x6)")
     ap.add_argument("--profile-steps", type=int, default=5)
@@ -308,7 +312,10 @@ def main():
 
     wl = WORKLOADS[args.workload]
     N, d = wl["N"], (1.0, 1.0, 1.0)
-    lo, n, g = synth.uniform_decomposition(N, wl["nbox"], wl["guard"])
+    if wl["nbox"] is None:
+        lo, n, g = synth.uneven_decomposition(N, case=4)
+    else:
+        lo, n, g = synth.uniform_decomposition(N, wl["nbox"], wl["guard"])
     p, dt, c = wl["p"], wl["dt"], 1.0
     log(f"[bench] workload {args.workload}: {wl['desc']}")
     E0, B0, J0 = make_inputs(N, d, case=2)
@@ -444,6 +451,25 @@ def main():
         log(f"[bench] PSATD-global: {1e3 * t / args.steps:.3f} ms/step")
         plan.close()
         del E, B, J, glob
+        torch.cuda.empty_cache()
+    if not args.no_heat:
+        # the same local-FFT push for the heat equation (one field, D = 0.1)
+        log(f"[bench] heat equation {head}: {args.warmup} warmup + {args.steps} timed steps")
+        plan = psatd.Plan(N, d, lo, n, g, p, dt, c, precision=head)
+        glob = [torch.from_numpy(np.ascontiguousarray(E0[0])).to("cuda", torch.float32).reshape(-1)] * 3
+        u = plan.empty_fields()
+        plan.scatter(glob, u)
+        plan.heat_run(u[0], 0.1, max(args.warmup, 1))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.heat_run(u[0], 0.1, args.steps)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out["heat_equation"] = {"ms_per_step": 1e3 * t / args.steps, "value": interior * args.steps / t,
+                                "precision": head, "diffusivity": 0.1}
+        log(f"[bench] heat equation: {1e3 * t / args.steps:.3f} ms/step")
+        plan.close()
+        del u, glob
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle, bounded sample)")

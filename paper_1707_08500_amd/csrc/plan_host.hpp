@@ -496,11 +496,21 @@ inline psatd_status build_host(HostTables& h, std::string& err, const int64_t gr
   prefix(h.itemsXI, [](const BoxD& b) { return (int64_t)b.n[2] * 6 * ((b.n[1] + kRB - 1) / kRB); });
   build_push(h);
   set_batches(h, 0);
-  // launch-shape defaults measured on the 96^3 local boxes: FP32 runs 256-thread
-  // x/y groups with radix-16 stages and 1024-thread z tiles; FP64 (twice the
-  // registers per value) runs 512-thread x/y groups with stages of radix <= 8
-  h.ntu = (f64 || h.spl) ? 512 : 1024;  // the matrix-core z tiles spill at 1024 threads
-  h.ntxy = f64 ? 512 : 256;
+  // launch-shape defaults (measured on 96^3 and 176^3 boxes): x/y groups of
+  // the fewest threads that still keep 16 waves on a CU given how many planes
+  // fit its LDS (96^3 FP32: four 40 KB planes x 256 threads; 176^3 FP32: one
+  // 127 KB plane x 1024 threads); 1024-thread z tiles in FP32 (the
+  // matrix-core z tiles spill there: 512); FP64 stages of radix <= 8
+  h.ntu = (f64 || h.spl) ? 512 : 1024;
+  {
+    const int per_cu = h.ldsF > 0 ? std::max(1, kMaxDynLds / h.ldsF) : 1;
+    h.ntxy = 1024;
+    for (int nt : {256, 512})
+      if (per_cu * nt / 64 >= 16) {
+        h.ntxy = nt;
+        break;
+      }
+  }
   if (f64 && !set_max_radix(h, 8)) return bad(PSATD_E_UNSUPPORTED, "no radix-8 schedule");
   return PSATD_OK;
 }

@@ -624,7 +624,8 @@ psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
       break;
     }
     case PSATD_TUNE_XY_THREADS:
-      if (value != 256 && value != 512) return fail(p, PSATD_E_INVALID, "x/y threads must be 256 or 512");
+      if (value != 256 && value != 512 && value != 1024)
+        return fail(p, PSATD_E_INVALID, "x/y threads must be 256, 512 or 1024");
       p->h.ntxy = value;
       d.ntxy = value;
       break;
@@ -712,9 +713,11 @@ psatd_status psatd_autotune(psatd_plan_t p, void* const E[3], void* const B[3], 
     int cxy = 256, cpb = p->h.PB, czt = 512, cx = 1;
     for (int xcd : {1, 0}) {
       if ((r = psatd_set_tuning(p, PSATD_TUNE_XCD_REMAP, xcd)) != PSATD_OK) return r;
-      for (int xy : {256, 512}) {
+      for (int xy : {256, 512, 1024}) {
+        // the split x/y passes run fixed 256-thread groups: one x/y shape to time
+        if (p->h.split && xy != 256) continue;
         if ((r = psatd_set_tuning(p, PSATD_TUNE_XY_THREADS, xy)) != PSATD_OK) return r;
-        for (int pb : {16, 8}) {
+        for (int pb : {16, 8, 4}) {
           if (psatd_set_tuning(p, PSATD_TUNE_Z_PENCILS, pb) != PSATD_OK) continue;
           for (int zt : {512, 1024}) {
             if ((r = psatd_set_tuning(p, PSATD_TUNE_Z_THREADS, zt)) != PSATD_OK) return r;
@@ -737,6 +740,7 @@ psatd_status psatd_autotune(psatd_plan_t p, void* const E[3], void* const B[3], 
   }
   for (int i = 0; i < 5; ++i)
     if ((r = psatd_set_tuning(p, keys[i], best[i])) != PSATD_OK) return r;
+  if (best_total >= 1e299) return fail(p, PSATD_E_STATE, "no launch shape could be timed");
   if (best_ms) *best_ms = best_total;
   if (cache_path) {
     std::ofstream out(cache_path, std::ios::app);

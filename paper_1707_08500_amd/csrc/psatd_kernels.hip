@@ -188,11 +188,14 @@ static hipError_t with_spl(int spl, F f) {
 template <typename T, int MAXR, int SPL>
 static hipError_t prepare_t(int ldsF, int ldsI, int ldsU, int ldsX, int ldsY) {
   constexpr bool I = IncOf<T>::value;
-  const void* xy[] = {(const void*)k_fwd_xy<T, 256, MAXR, SPL>, (const void*)k_fwd_xy<T, 512, MAXR, SPL>};
+  const void* xy[] = {(const void*)k_fwd_xy<T, 256, MAXR, SPL>, (const void*)k_fwd_xy<T, 512, MAXR, SPL>,
+                      (const void*)k_fwd_xy<T, 1024, MAXR, SPL>};
   const void* inv[] = {(const void*)k_inv_xy<T, I, 256, MAXR, SPL, false>,
                        (const void*)k_inv_xy<T, I, 512, MAXR, SPL, false>,
+                       (const void*)k_inv_xy<T, I, 1024, MAXR, SPL, false>,
                        (const void*)k_inv_xy<T, I, 256, MAXR, SPL, true>,
-                       (const void*)k_inv_xy<T, I, 512, MAXR, SPL, true>};
+                       (const void*)k_inv_xy<T, I, 512, MAXR, SPL, true>,
+                       (const void*)k_inv_xy<T, I, 1024, MAXR, SPL, true>};
   const void* upd[] = {(const void*)k_z_update<T, 512, 8, I, MAXR, SPL>,
                        (const void*)k_z_update<T, 512, 16, I, MAXR, SPL>,
                        (const void*)k_z_update<T, 1024, 8, I, MAXR, SPL>,
@@ -301,6 +304,9 @@ static hipError_t fwd_t(const DevPlan& p, const Batch& b, void* const* in9, void
   if (!g) return hipSuccess;
   return with_spl<T>(p.spl, [&](auto sc) -> hipError_t {
     constexpr int SPL = decltype(sc)::value;
+    if (p.ntxy == 1024)
+      PSATD_MAXR_SWITCH(SPL, return (fwd_go<T, 1024, 8, SPL>(p, b, a, g, st)),
+                        return (fwd_go<T, 1024, 16, SPL>(p, b, a, g, st)));
     if (p.ntxy == 512)
       PSATD_MAXR_SWITCH(SPL, return (fwd_go<T, 512, 8, SPL>(p, b, a, g, st)),
                         return (fwd_go<T, 512, 16, SPL>(p, b, a, g, st)));
@@ -383,6 +389,9 @@ static hipError_t inv_t(const DevPlan& p, const Batch& b, const void* spec, void
   if (!g) return hipSuccess;
   return with_spl<T>(p.spl, [&](auto sc) -> hipError_t {
     constexpr int SPL = decltype(sc)::value;
+    if (p.ntxy == 1024)
+      PSATD_MAXR_SWITCH(SPL, return (inv_go<T, 1024, 8, SPL>(p, b, a, g, st)),
+                        return (inv_go<T, 1024, 16, SPL>(p, b, a, g, st)));
     if (p.ntxy == 512)
       PSATD_MAXR_SWITCH(SPL, return (inv_go<T, 512, 8, SPL>(p, b, a, g, st)),
                         return (inv_go<T, 512, 16, SPL>(p, b, a, g, st)));

@@ -434,7 +434,7 @@ def test_launch_shapes_do_not_change_results(tmp_path):
     E, B, J = random_fields(N, 12, p=16)
     case = GpuCase(N, lo, n, g, 16, 0.5, 1.0, "f64", "replicated", E, B, J)
     ref = None
-    settings = [dict(), dict(max_radix=8), dict(xy_threads=512), dict(z_threads=1024),
+    settings = [dict(), dict(max_radix=8), dict(xy_threads=512), dict(xy_threads=1024), dict(z_threads=1024),
                 dict(z_pencils=8), dict(xcd_remap=0), dict(fuse_eb=0), dict(batch_boxes=3),
                 dict(grid_fwd=100, grid_upd=64, grid_inv=96, grid_exch=50),
                 dict(max_radix=8, xy_threads=512, z_threads=1024, batch_boxes=2)]
