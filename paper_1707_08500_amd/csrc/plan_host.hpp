@@ -455,7 +455,9 @@ inline psatd_status build_host(HostTables& h, std::string& err, const int64_t gr
     return bad(PSATD_E_UNSUPPORTED, "padded lengths too large for the split x/y passes");
   // z-update tile: PB consecutive (ky, kx) pencils (128-byte rows when possible)
   {
-    int PB = f64 ? 8 : 16;
+    // 8 pencils (64-byte FP32 / 128-byte FP64 rows): two FP32 96^3 tiles fit a
+    // CU's LDS, so one tile's loads overlap the other's transforms
+    int PB = 8;
     while (PB > 4 && !z_tile_fits(h, maxPz, PB)) PB /= 2;
     if (!z_tile_fits(h, maxPz, PB))
       return bad(PSATD_E_UNSUPPORTED, "padded z length too large for the z-update kernel");
@@ -499,9 +501,9 @@ inline psatd_status build_host(HostTables& h, std::string& err, const int64_t gr
   // launch-shape defaults (measured on 96^3 and 176^3 boxes): x/y groups of
   // the fewest threads that still keep 16 waves on a CU given how many planes
   // fit its LDS (96^3 FP32: four 40 KB planes x 256 threads; 176^3 FP32: one
-  // 127 KB plane x 1024 threads); 1024-thread z tiles in FP32 (the
-  // matrix-core z tiles spill there: 512); FP64 stages of radix <= 8
-  h.ntu = (f64 || h.spl) ? 512 : 1024;
+  // 127 KB plane x 1024 threads); 512-thread z tiles of 8 pencils; FP64
+  // stages of radix <= 8
+  h.ntu = 512;
   {
     const int per_cu = h.ldsF > 0 ? std::max(1, kMaxDynLds / h.ldsF) : 1;
     h.ntxy = 1024;
