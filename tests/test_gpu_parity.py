@@ -174,6 +174,20 @@ def test_step_infinite_order_and_odd_lengths():
 
 
 @pytest.mark.parametrize("precision,tol", [("f64", TOL64), ("f32", TOL32)])
+@pytest.mark.parametrize("p", [2, 0])
+def test_step_anisotropic_general_c_negative_dt(precision, tol, p):
+    """dx != dy != dz, c = 1.7, dt < 0 (a step backwards in time), the lowest
+    finite order and infinite order, deposited currents, 3 steps."""
+    say(f"anisotropic d, c=1.7, dt=-0.35, p={p}, {precision}")
+    N = (24, 20, 18)
+    d = (0.7, 1.3, 0.9)
+    lo, n, g = synth.uniform_decomposition(N, (2, 2, 1), 3)
+    fields = random_fields(N, 18 + p, d=d, p=p)
+    case, eE, eB, _ = run_both(N, lo, n, g, p, -0.35, 1.7, precision, "deposited", fields, 3, d=d)
+    check(case, eE, eB, precision, tol)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", TOL64), ("f32", TOL32)])
 def test_step_local_96_cubed(precision, tol):
     """The configuration-2 local shape (64^3 + 16 guards = 96^3, p = 32) on a
     128^3 grid of 2x2x2 boxes with the configuration-2 input recipe."""
@@ -551,3 +565,45 @@ def test_psatd_global_on_gpu(precision, tol):
         for a in range(3):
             assert O.rel_l2(gE[a], oE[a]) <= tol
             assert O.rel_l2(gB[a], oB[a]) <= tol
+
+
+# ------------------------------------------ workspace, stream, profiled run
+def test_caller_workspace_side_stream_and_profiled_run_are_the_same_step():
+    """A caller-provided workspace on a non-default stream, and the profiled
+    (event-bracketed, eager) run, give the same bytes as the plan-owned
+    workspace on the current stream; a too-small workspace is rejected."""
+    import torch
+    from paper_1707_08500_amd import psatd
+    say("caller workspace, side stream, profiled run")
+    N = (32, 24, 20)
+    lo, n, g = synth.uniform_decomposition(N, (2, 2, 1), 4)
+    E, B, J = random_fields(N, 19, p=8)
+    outs = []
+    for mode in ("plan", "caller", "profiled"):
+        case = GpuCase(N, lo, n, g, 8, 0.5, 1.0, "f32", "replicated", E, B, J)
+        plan = case.plan
+        if mode == "caller":
+            need = plan.workspace_bytes()
+            assert need > 0
+            with pytest.raises(psatd.PsatdError):
+                plan.set_workspace(torch.empty(need // 2, dtype=torch.uint8, device="cuda"))
+            ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+            plan.set_workspace(ws)
+            side = torch.cuda.Stream()
+            torch.cuda.synchronize()
+            plan.set_stream(side.cuda_stream)
+            plan.run(case.E, case.B, case.J, 2)
+            side.synchronize()
+        elif mode == "profiled":
+            ph = plan.run_profiled(case.E, case.B, case.J, 2)
+            assert set(ph) == set(psatd.PHASES)
+            assert all(v >= 0.0 for v in ph.values()) and sum(ph.values()) > 0.0
+            plan.sync()
+        else:
+            plan.run(case.E, case.B, case.J, 2)
+            plan.sync()
+        outs.append([x.cpu() for x in case.E + case.B])
+        plan.close()
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            assert torch.equal(a, b)
