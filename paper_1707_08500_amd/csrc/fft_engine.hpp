@@ -161,16 +161,22 @@ PSATD_HD uint32_t fdiv(uint32_t n, FastDiv f) {
 }
 
 // One FFT length's schedule.  Stage s has radix r_s and stride
-// ms_s = N / (r_0 ... r_s); twiddles live in the plan's table at offset tw.
+// ms_s = N / (r_0 ... r_s).  The plan's twiddle table (offset tw, N entries,
+// forward sign) is laid out by stage and butterfly: stage s, butterfly offset
+// j < ms_s, output t = 1..r_s-1 holds W_N^{j t r_0...r_{s-1}} at
+//   twoff[s] + j (r_s - 1) + t - 1,
+// so one butterfly reads r_s - 1 consecutive entries (one base address); the
+// stages take sum_s ms_s (r_s - 1) = N - 1 entries, the last one is 1.
 struct FftPlanD {
   int32_t N;
   int32_t nstages;
   int32_t radix[kMaxStages];
   int32_t stride[kMaxStages];   // ms_s
   int32_t prod[kMaxStages];     // r_0 ... r_{s-1}
+  int32_t twoff[kMaxStages];    // start of stage s in the plan's twiddle table
   FastDiv rdiv[kMaxStages];     // division by r_s
   FastDiv sdiv[kMaxStages];     // division by ms_s
-  int32_t tw;    // offset of W_N^e = exp(-2 pi i e / N), e = 0..N-1, in the twiddle table
+  int32_t tw;    // offset of the plan's twiddle table
   int32_t pad_;
 };
 
@@ -208,13 +214,13 @@ PSATD_HD cx<T> twid(const cx<T>* tw, int e) {
 
 // One stage over M transforms; element e of transform m at buf[m*ms + e*es].
 // Sub-transform length L, stride L/R.  Butterflies are distributed with the
-// transform index fastest across threads.
+// transform index fastest across threads.  tws: this stage's twiddles (R - 1
+// per butterfly offset j, see FftPlanD).
 template <int R, int DIR, bool DIF, typename T>
 PSATD_HD void fft_stage(cx<T>* buf, int M, FastDiv dM, int ms, int es, int N, int L, FastDiv dS,
-                        const cx<T>* tw, int tid, int nt) {
+                        const cx<T>* tws, int tid, int nt) {
   const int mstride = L / R;
   const int nb = N / R;
-  const int twstep = N / L;
   const int total = M * nb;
   if (tid >= total) return;
   // butterfly b = w M + m, advanced incrementally by nt per iteration
@@ -227,7 +233,7 @@ PSATD_HD void fft_stage(cx<T>* buf, int M, FastDiv dM, int ms, int es, int N, in
     const int blk = (int)fdiv((uint32_t)w, dS);
     const int j = w - blk * mstride;
     cx<T>* p = buf + m * ms + (blk * L + j) * es;
-    const int jt = j * twstep;
+    const cx<T>* tb = tws + j * (R - 1) - 1;  // tb[t] = W^{j t ...}, t = 1..R-1
     cx<T> a[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) a[q] = p[q * step];
@@ -235,12 +241,12 @@ PSATD_HD void fft_stage(cx<T>* buf, int M, FastDiv dM, int ms, int es, int N, in
       Dft<R, DIR, T>::run(a);
       if (j) {
 #pragma unroll
-        for (int t = 1; t < R; ++t) a[t] = cmul(a[t], twid<DIR>(tw, jt * t));
+        for (int t = 1; t < R; ++t) a[t] = cmul(a[t], twid<DIR>(tb, t));
       }
     } else {
       if (j) {
 #pragma unroll
-        for (int t = 1; t < R; ++t) a[t] = cmul(a[t], twid<DIR>(tw, jt * t));
+        for (int t = 1; t < R; ++t) a[t] = cmul(a[t], twid<DIR>(tb, t));
       }
       Dft<R, DIR, T>::run(a);
     }
@@ -276,7 +282,7 @@ PSATD_HD void fft_stage_dispatch(int R, cx<T>* buf, int M, FastDiv dM, int ms, i
   }
 }
 
-// natural -> stage-digit order; ends with a barrier.  tw: this plan's W_N^e
+// natural -> stage-digit order; ends with a barrier.  tw: this plan's twiddle
 // table (global or LDS).  The plan is read from uniform memory.
 template <int DIR, int MAXR, typename T, class Bar>
 PSATD_HD void fft_dif(cx<T>* buf, int M, int ms, int es, const FftPlanD* pl, const cx<T>* tw,
@@ -287,7 +293,8 @@ PSATD_HD void fft_dif(cx<T>* buf, int M, int ms, int es, const FftPlanD* pl, con
   int L = N;
   for (int s = 0; s < ns; ++s) {
     const int R = pl->radix[s];
-    fft_stage_dispatch<DIR, true, MAXR, T>(R, buf, M, dM, ms, es, N, L, pl->sdiv[s], tw, tid, nt);
+    fft_stage_dispatch<DIR, true, MAXR, T>(R, buf, M, dM, ms, es, N, L, pl->sdiv[s], tw + pl->twoff[s], tid,
+                                           nt);
     bar();
     L /= R;
   }
@@ -302,8 +309,8 @@ PSATD_HD void fft_dit(cx<T>* buf, int M, int ms, int es, const FftPlanD* pl, con
   const FastDiv dM = make_fastdiv((uint32_t)M);
   for (int s = ns - 1; s >= 0; --s) {
     const int L = pl->stride[s] * pl->radix[s];
-    fft_stage_dispatch<DIR, false, MAXR, T>(pl->radix[s], buf, M, dM, ms, es, N, L, pl->sdiv[s], tw, tid,
-                                      nt);
+    fft_stage_dispatch<DIR, false, MAXR, T>(pl->radix[s], buf, M, dM, ms, es, N, L, pl->sdiv[s],
+                                            tw + pl->twoff[s], tid, nt);
     bar();
   }
 }

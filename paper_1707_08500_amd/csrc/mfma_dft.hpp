@@ -85,7 +85,8 @@ PSATD_HD Dft16Operand<SPL> dft16_operand(int lane) {
 }
 
 // One radix-16 stage (the first of the transform) on the matrix cores.
-// DIF: DFT then twiddle W_N^{j t}; DIT: twiddle W_N^{j q} then DFT.  In place;
+// DIF: DFT then twiddle W_N^{j t}; DIT: twiddle W_N^{j q} then DFT, with
+// W_N^{j u} at tw[15 j + u - 1] (the first stage's part of the table).  In place;
 // every wave takes whole 16-column chunks, all waves run the same number of
 // chunk iterations (idle lanes load zeros and store nothing), so a model of
 // the instruction that synchronises the work-group sees uniform calls.
@@ -114,7 +115,7 @@ PSATD_HD void dft16_mfma(cx<float>* buf, int M, FastDiv dM, int ms, int es, int 
     for (int r = 0; r < 4; ++r) {
       const int q = 4 * quad + r;
       cx<float> x = act ? p[q * step] : cx<float>{0.f, 0.f};
-      if (!DIF && j) x = cmul(x, twid<DIR>(tw, j * q));
+      if (!DIF && j && q) x = cmul(x, twid<DIR>(tw, 15 * j + q - 1));
       __bf16 hr[SPL], hi[SPL];
       split_bf16<SPL>(x.x, hr);
       split_bf16<SPL>(x.y, hi);
@@ -144,7 +145,7 @@ PSATD_HD void dft16_mfma(cx<float>* buf, int M, FastDiv dM, int ms, int es, int 
     for (int r = 0; r < 4; ++r) {
       const int t = 4 * quad + r;
       cx<float> y{yr[r], yi[r]};
-      if (DIF && j) y = cmul(y, twid<DIR>(tw, j * t));
+      if (DIF && j && t) y = cmul(y, twid<DIR>(tw, 15 * j + t - 1));
       if (act) p[t * step] = y;
     }
   }
@@ -168,7 +169,8 @@ PSATD_HD void fft_dif_mfma(cx<float>* buf, int M, int ms, int es, const FftPlanD
   }
   for (; s < ns; ++s) {
     const int R = pl->radix[s];
-    fft_stage_dispatch<DIR, true, MAXR, float>(R, buf, M, dM, ms, es, N, L, pl->sdiv[s], tw, tid, nt);
+    fft_stage_dispatch<DIR, true, MAXR, float>(R, buf, M, dM, ms, es, N, L, pl->sdiv[s], tw + pl->twoff[s],
+                                               tid, nt);
     bar();
     L /= R;
   }
@@ -183,8 +185,8 @@ PSATD_HD void fft_dit_mfma(cx<float>* buf, int M, int ms, int es, const FftPlanD
   const bool gemm = ns > 0 && pl->radix[0] == 16;
   for (int s = ns - 1; s >= (gemm ? 1 : 0); --s) {
     const int L = pl->stride[s] * pl->radix[s];
-    fft_stage_dispatch<DIR, false, MAXR, float>(pl->radix[s], buf, M, dM, ms, es, N, L, pl->sdiv[s], tw,
-                                                tid, nt);
+    fft_stage_dispatch<DIR, false, MAXR, float>(pl->radix[s], buf, M, dM, ms, es, N, L, pl->sdiv[s],
+                                                tw + pl->twoff[s], tid, nt);
     bar();
   }
   if (gemm) {

@@ -144,6 +144,29 @@ inline bool small_primes_only(int64_t n) {
   return n == 1;
 }
 
+// Writes the N-entry twiddle table of a plan (at pl.tw) for its current radix
+// schedule: by stage and butterfly, W_N^{j t prod_s} for j < stride_s,
+// t = 1..radix_s-1, then ones up to N entries.  Sets pl.twoff.
+inline void write_plan_twiddles(HostTables& h, FftPlanD& pl) {
+  const int N = pl.N;
+  const long double PI = 3.141592653589793238462643383279502884L;
+  int o = 0;
+  for (int st = 0; st < kMaxStages; ++st) {
+    pl.twoff[st] = o;
+    if (st >= pl.nstages) continue;
+    for (int j = 0; j < pl.stride[st]; ++j)
+      for (int t = 1; t < pl.radix[st]; ++t, ++o) {
+        const int64_t e = (int64_t)j * t * pl.prod[st];  // < N
+        h.twr[pl.tw + o] = cosl(2.0L * PI * e / N);
+        h.twi[pl.tw + o] = -sinl(2.0L * PI * e / N);
+      }
+  }
+  for (; o < N; ++o) {  // the stages take N - 1 entries
+    h.twr[pl.tw + o] = 1.0L;
+    h.twi[pl.tw + o] = 0.0L;
+  }
+}
+
 // Adds (or finds) an FFT plan of length N; returns its index or -1.
 inline int add_plan(HostTables& h, int N) {
   for (size_t i = 0; i < h.plans.size(); ++i)
@@ -154,11 +177,9 @@ inline int add_plan(HostTables& h, int N) {
   pl.N = N;
   set_stages(pl, rad);
   pl.tw = (int32_t)h.twr.size();
-  const long double PI = 3.141592653589793238462643383279502884L;
-  for (int e = 0; e < N; ++e) {
-    h.twr.push_back(cosl(2.0L * PI * e / N));
-    h.twi.push_back(-sinl(2.0L * PI * e / N));
-  }
+  h.twr.resize(h.twr.size() + N);
+  h.twi.resize(h.twi.size() + N);
+  write_plan_twiddles(h, pl);
   h.plans.push_back(pl);
   return (int)h.plans.size() - 1;
 }
@@ -245,6 +266,7 @@ inline bool set_max_radix(HostTables& h, int maxr) {
     if (!schedule(pl.N, rad, maxr, h.spl)) return false;
     set_stages(pl, rad);
   }
+  for (FftPlanD& pl : plans) write_plan_twiddles(h, pl);  // the layout follows the schedule
   h.plans = plans;
   h.maxr = maxr;
   return true;

@@ -65,6 +65,24 @@ psatd_status fail(psatd_plan_t p, psatd_status st, const std::string& m) {
                   std::string(#call) + ": " + hipGetErrorString(e_));                         \
   } while (0)
 
+// The twiddle tables in the plan's device type (FP64 or FP32 pairs).
+std::vector<unsigned char> device_twiddles(const HostTables& h) {
+  const size_t n = h.twr.size();
+  std::vector<unsigned char> out;
+  if (is_f64(h.prec)) {
+    std::vector<cx<double>> t(n);
+    for (size_t i = 0; i < n; ++i) t[i] = {(double)h.twr[i], (double)h.twi[i]};
+    out.assign(reinterpret_cast<const unsigned char*>(t.data()),
+               reinterpret_cast<const unsigned char*>(t.data() + n));
+  } else {
+    std::vector<cx<float>> t(n);
+    for (size_t i = 0; i < n; ++i) t[i] = {(float)h.twr[i], (float)h.twi[i]};
+    out.assign(reinterpret_cast<const unsigned char*>(t.data()),
+               reinterpret_cast<const unsigned char*>(t.data() + n));
+  }
+  return out;
+}
+
 int64_t workspace_need(const psatd_plan_s* p) {
   return 9 * p->h.batch_slab * (int64_t)(2 * real_size(p->h.prec));
 }
@@ -274,14 +292,9 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   };
   put(o_box, h.box.data(), h.box.size() * sizeof(BoxD));
   put(o_plan, h.plans.data(), h.plans.size() * sizeof(FftPlanD));
-  if (f64) {
-    std::vector<cx<double>> t(h.twr.size());
-    for (size_t i = 0; i < t.size(); ++i) t[i] = {(double)h.twr[i], (double)h.twi[i]};
-    put(o_tw, t.data(), t.size() * sizeof(cx<double>));
-  } else {
-    std::vector<cx<float>> t(h.twr.size());
-    for (size_t i = 0; i < t.size(); ++i) t[i] = {(float)h.twr[i], (float)h.twi[i]};
-    put(o_tw, t.data(), t.size() * sizeof(cx<float>));
+  {
+    const std::vector<unsigned char> t = device_twiddles(h);
+    put(o_tw, t.data(), t.size());
   }
   put(o_kent, h.kent.data(), h.kent.size() * sizeof(KEntry));
   put(o_nbo, h.nbr_off.data(), h.nbr_off.size() * 4);
@@ -618,7 +631,13 @@ psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
       HIPCHK(p, hipStreamSynchronize(p->stream));
       HIPCHK(p, hipMemcpy(const_cast<FftPlanD*>(d.plans), trial.plans.data(),
                           trial.plans.size() * sizeof(FftPlanD), hipMemcpyHostToDevice));
+      {  // the twiddle tables follow the radix schedule
+        const std::vector<unsigned char> t = device_twiddles(trial);
+        HIPCHK(p, hipMemcpy(const_cast<void*>(d.tw), t.data(), t.size(), hipMemcpyHostToDevice));
+      }
       p->h.plans = trial.plans;
+      p->h.twr = trial.twr;
+      p->h.twi = trial.twi;
       p->h.maxr = value;
       d.maxr = value;
       break;
