@@ -67,11 +67,15 @@ def make_inputs(N, d, case):
 
 
 def algorithmic_bytes(plan, dec_lo, dec_n, dec_g, sb):
-    """Bytes each phase must move at least once, per launch (one step).  With
+    """Bytes each phase must move at least once, per launch (one step).  The z
+    pass reads 9 complex fields at every k-point and writes the 6 results on the
+    interior z-planes only (all the inverse pass reads).  The FP32 forms add
+    increments, so their inverse pass reads and writes the interior cells.  With
     the fused E,B exchange the inverse pass also writes every guard copy (no
     read), and the exchange phase moves nothing."""
     import numpy as np
     fused = bool(plan.tuning()["fuse_eb"])
+    inc = plan.precision != "f64"
     out = dict(exchange_J=0, fft_xy_fwd=0, z_update=0, fft_xy_inv=0, exchange_EB=0)
     kpoints = 0
     for s in range(len(dec_lo)):
@@ -82,8 +86,8 @@ def algorithmic_bytes(plan, dec_lo, dec_n, dec_g, sb):
         guard = V - nx * ny * nz
         out["exchange_J"] += guard * 3 * 2 * sb
         out["fft_xy_fwd"] += 9 * V * sb + 9 * pz * py * H * 2 * sb
-        out["z_update"] += pz * py * H * 15 * 2 * sb
-        out["fft_xy_inv"] += 6 * nz * py * H * 2 * sb + 6 * nz * ny * nx * sb
+        out["z_update"] += (9 * pz + 6 * nz) * py * H * 2 * sb
+        out["fft_xy_inv"] += 6 * nz * py * H * 2 * sb + (2 if inc else 1) * 6 * nz * ny * nx * sb
         if fused:
             out["fft_xy_inv"] += guard * 6 * sb
         else:

@@ -420,8 +420,13 @@ PSATD_HD void body_z_update(const UpdArgs<T>& a, int item, int tid, int nt, cx<T
   bar();
   eng.template dit<+1, MAXR>(lds, 6 * PB, 1, W, plz, twz, tid, nt, bar);
 
-  cx<T>* dst = a.spec + (bx.soff - a.sbias) + q0;
-  copy_grid3<8, cx<T>>(6, Pz, PB, tid, nt, [&](int, int f, int z, int p) { return lds[z * W + f * PB + p]; },
+  // only the interior z-planes: the inverse pass reads nothing else (the guard
+  // planes of E and B are rewritten by the exchange)
+  const int gz = bx.g[2];
+  cx<T>* dst = a.spec + (bx.soff - a.sbias) + q0 + (int64_t)gz * nq;
+  const cx<T>* res = lds + gz * W;
+  copy_grid3<8, cx<T>>(6, bx.n[2], PB, tid, nt,
+                       [&](int, int f, int z, int p) { return res[z * W + f * PB + p]; },
                        [&](int, int f, int z, int p, cx<T> v) {
                          if (p < np) dst[f * slab + (int64_t)z * nq + p] = v;
                        });
@@ -489,10 +494,12 @@ PSATD_HD void body_z_heat(const HeatArgs<T>& a, int item, int tid, int nt, cx<T>
   }
   bar();
   eng.template dit<+1, MAXR>(lds, PB, 1, PB, plz, twz, tid, nt, bar);
-  copy_batched<8, cx<T>>(ndata, tid, nt, [&](int i) { return lds[i]; },
+  // interior z-planes only (all the inverse pass reads)
+  const int gz = bx.g[2];
+  copy_batched<8, cx<T>>(bx.n[2] * PB, tid, nt, [&](int i) { return lds[gz * PB + i]; },
                          [&](int i, cx<T> v) {
                            const int p = i % PB;
-                           if (p < np) col[(int64_t)(i / PB) * nq + p] = v;
+                           if (p < np) col[(int64_t)(gz + i / PB) * nq + p] = v;
                          });
 }
 
