@@ -264,6 +264,29 @@ def test_graph_run_equals_eager_steps_and_is_deterministic():
         assert bool((x == y).all())
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16x6"])
+@pytest.mark.parametrize("grid_fwd", [0, 37])
+def test_graph_run_equals_single_steps(precision, grid_fwd):
+    """Graph-captured runs (3 + 2 steps) give the bytes of 5 single steps in
+    every precision form: uneven boxes, replicated J, one group per work item
+    or a persistent forward grid of 37 groups."""
+    say(f"graph run vs single steps {precision} grid_fwd={grid_fwd}")
+    N, lo, n, g = uneven_small()
+    E, B, J = random_fields(N, 23, p=4)
+    a = GpuCase(N, lo, n, g, 4, 0.3, 1.0, precision, "replicated", E, B, J)
+    b = GpuCase(N, lo, n, g, 4, 0.3, 1.0, precision, "replicated", E, B, J)
+    for case in (a, b):
+        case.plan.set_tuning(grid_fwd=grid_fwd)
+    for _ in range(5):
+        a.plan.step(a.E, a.B, a.J)
+    b.plan.run(b.E, b.B, b.J, 3)
+    b.plan.run(b.E, b.B, b.J, 2)
+    a.plan.sync()
+    b.plan.sync()
+    for x, y in zip(a.E + a.B + a.J, b.E + b.B + b.J):
+        assert bool((x == y).all())
+
+
 def test_guards_consistent_after_steps():
     say("consistency after steps")
     N, lo, n, g = uneven_small()
