@@ -196,6 +196,42 @@ def summarize_ktrace(stats_csv, bench_line, workload, command):
     return "\n".join(lines) + "\n"
 
 
+def summarize_mix(a_csv, b_csv, workload, command):
+    """VALU instruction mix per dispatch of every psatd kernel from two
+    rocprofv3 --pmc passes: SQ_INSTS_VALU, the F64 kinds, SQ_INSTS_LDS,
+    SQ_INSTS_SALU and SQ_INSTS_VALU_INT32 in the first, the F32 kinds and
+    SQ_INSTS_VALU_CVT in the second (wave instructions, mean over dispatches)."""
+    per = {}
+    for path in (a_csv, b_csv):
+        for r in csv.DictReader(open(path)):
+            if "psatd" not in r["Kernel_Name"]:
+                continue
+            short = r["Kernel_Name"].split("(")[0].replace("void ", "").strip()
+            per.setdefault(short, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    mean = {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in per.items()}
+    lines = [f"# VALU instruction mix per dispatch (wave instructions), workload {workload}, FP32 VALU form",
+             f"# command: {command}",
+             f"source_digest: {source_digest()}",
+             "# kernel | VALU | INT32 | F32 (add+mul+fma) | F64 (add+mul+fma+trans) | CVT | other VALU | "
+             "SALU | LDS"]
+    for k in sorted(mean):
+        d = mean[k]
+        if "SQ_INSTS_VALU" not in d:
+            continue
+        v = d["SQ_INSTS_VALU"]
+        i32 = d.get("SQ_INSTS_VALU_INT32", 0.0)
+        f32 = sum(d.get(c, 0.0) for c in ("SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_MUL_F32",
+                                           "SQ_INSTS_VALU_FMA_F32"))
+        f64 = sum(d.get(c, 0.0) for c in ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64",
+                                           "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_TRANS_F64"))
+        cvt = d.get("SQ_INSTS_VALU_CVT", 0.0)
+        other = max(0.0, v - i32 - f32 - f64 - cvt)
+        pct = (lambda x: f"{x:.3g} ({100 * x / v:.0f}%)") if v else (lambda x: f"{x:.3g}")
+        lines.append(f"{k} | {v:.3g} | {pct(i32)} | {pct(f32)} | {pct(f64)} | {pct(cvt)} | {pct(other)} | "
+                     f"{d.get('SQ_INSTS_SALU', 0.0):.3g} | {d.get('SQ_INSTS_LDS', 0.0):.3g}")
+    return "\n".join(lines) + "\n"
+
+
 SPL_OF = {"f32": 0, "bf16x3": 2, "bf16x6": 3}
 
 
@@ -278,6 +314,8 @@ def main():
     ap.add_argument("--pmc-command", default="", help="the profiled command, recorded in the summary")
     ap.add_argument("--summarize-ktrace", nargs=2, metavar=("KERNEL_STATS_CSV", "BENCH_LOG"),
                     help="print the kernel-statistics summary of a rocprofv3 --stats run and exit")
+    ap.add_argument("--summarize-mix", nargs=2, metavar=("PASS_A_CSV", "PASS_B_CSV"),
+                    help="print the VALU instruction-mix summary of two rocprofv3 --pmc runs and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -294,6 +332,10 @@ def main():
             if line.startswith("{"):
                 bench_line = line
         print(summarize_ktrace(args.summarize_ktrace[0], bench_line, args.workload, args.pmc_command),
+              end="")
+        return
+    if args.summarize_mix:
+        print(summarize_mix(args.summarize_mix[0], args.summarize_mix[1], args.workload, args.pmc_command),
               end="")
         return
     if args.gpus != 1:
