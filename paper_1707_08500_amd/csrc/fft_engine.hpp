@@ -337,7 +337,7 @@ struct FftValu {
 //   A[k] = E + W_N^k O,  A[Nh-k] = conj(E) + W_N^{Nh-k} conj(O).
 // twr: W_N^e table, N = 2 Nh.  k in [0, Nh/2].
 template <typename T>
-PSATD_HD void r2c_post(cx<T>* row, int k, int Nh, const cx<T>* twr) {
+PSATD_HD void r2c_post_w(cx<T>* row, int k, int Nh, cx<T> wk, cx<T> wp) {  // wk = W_N^k, wp = W_N^{Nh-k}
   if (k == 0) {
     const cx<T> z = row[0];
     row[0] = cx<T>{z.x + z.y, T(0)};
@@ -350,8 +350,12 @@ PSATD_HD void r2c_post(cx<T>* row, int k, int Nh, const cx<T>* twr) {
   const cx<T> E = scale(zk + cz, T(0.5));
   const cx<T> D = zk - cz;
   const cx<T> O = cx<T>{T(0.5) * D.y, T(-0.5) * D.x};
-  row[k] = E + cmul(twr[k], O);
-  if (kp != k) row[kp] = conj(E) + cmul(twr[kp], conj(O));
+  row[k] = E + cmul(wk, O);
+  if (kp != k) row[kp] = conj(E) + cmul(wp, conj(O));
+}
+template <typename T>
+PSATD_HD void r2c_post(cx<T>* row, int k, int Nh, const cx<T>* twr) {
+  r2c_post_w(row, k, Nh, twr[k], twr[Nh - k]);
 }
 
 // Inverse of r2c_post up to a factor 2: from A[0..Nh] builds
@@ -364,12 +368,42 @@ PSATD_HD cx<T> c2r_pair(cx<T> ak, cx<T> ap, cx<T> wk) {
 }
 
 template <typename T>
-PSATD_HD void c2r_pre(cx<T>* row, int k, int Nh, const cx<T>* twr) {
+PSATD_HD void c2r_pre_w(cx<T>* row, int k, int Nh, cx<T> wk, cx<T> wp) {  // wk = W_N^k, wp = W_N^{Nh-k}
   const int kp = Nh - k;
   const cx<T> ak = row[k], ap = row[kp];
-  const cx<T> zk = c2r_pair(ak, ap, twr[k]);
-  if (k != 0 && kp != k) row[kp] = c2r_pair(ap, ak, twr[kp]);
+  const cx<T> zk = c2r_pair(ak, ap, wk);
+  if (k != 0 && kp != k) row[kp] = c2r_pair(ap, ak, wp);
   row[k] = zk;
+}
+template <typename T>
+PSATD_HD void c2r_pre(cx<T>* row, int k, int Nh, const cx<T>* twr) {
+  c2r_pre_w(row, k, Nh, twr[k], twr[Nh - k]);
+}
+
+// The pair pass (r2c_post if FWD, else c2r_pre) over R rows (row r at
+// rows + r ld) of a work-group's plane: each thread keeps one k of the Nh/2 + 1
+// pairs with its two twiddles in registers and walks rows r0, r0 + per, ...
+template <bool FWD, typename T>
+PSATD_HD void pair_pass_rows(cx<T>* rows, int R, int ld, int Nh, const cx<T>* twr, int tid, int nt) {
+  const int np = Nh / 2 + 1;
+  if (np <= nt) {
+    const int per = nt / np;
+    const int r0 = tid / np;
+    if (r0 >= per) return;
+    const int k = tid - r0 * np;
+    const cx<T> wk = twr[k], wp = twr[Nh - k];
+    for (int r = r0; r < R; r += per) {
+      if (FWD) r2c_post_w(rows + r * ld, k, Nh, wk, wp);
+      else c2r_pre_w(rows + r * ld, k, Nh, wk, wp);
+    }
+    return;
+  }
+  const FastDiv dnp = make_fastdiv((uint32_t)np);
+  for (int i = tid; i < R * np; i += nt) {
+    const int r = (int)fdiv((uint32_t)i, dnp);
+    if (FWD) r2c_post(rows + r * ld, i - r * np, Nh, twr);
+    else c2r_pre(rows + r * ld, i - r * np, Nh, twr);
+  }
 }
 
 }  // namespace psatd

@@ -98,6 +98,12 @@ PSATD_HD void copy_batched(int total, int tid, int nt, Src src, Dst dst) {
   }
 }
 
+// Two neighbouring values accessed as one aligned vector.
+template <typename V>
+struct alignas(2 * sizeof(V)) Pair {
+  V a, b;
+};
+
 // Row-major R x C walk shared by a work-group: element i = tid + k nt, with
 // its (row, col) advanced incrementally (no per-element division); full
 // batches of U run without bounds checks.  get(i, r, c) -> V, put(i, r, c, v).
@@ -259,16 +265,22 @@ PSATD_HD void body_fwd_xy(const FwdArgs<T>& a, int item, int tid, int nt, cx<T>*
   const cx<T>* src = reinterpret_cast<const cx<T>*>(a.in[f] + bx.foff + (int64_t)z * Py * Px);
   for (int i = tid; i < Nh + Py + Px; i += nt)  // twx, twy, twr are contiguous
     twx[i] = i < Nh ? gtx[i] : (i < Nh + Py ? gty[i - Nh] : gtr[i - Nh - Py]);
-  copy_grid<8, cx<T>>(Py, Nh, tid, nt, [&](int i, int, int) { return src[i]; },
-                      [&](int, int y, int x, cx<T> v) { lds[y * ld + posx[x]] = v; });
+  if ((Nh & 1) == 0 && (reinterpret_cast<uintptr_t>(src) % sizeof(Pair<cx<T>>)) == 0) {
+    // two neighbouring complex values per access (rows of even length)
+    const Pair<cx<T>>* src2 = reinterpret_cast<const Pair<cx<T>>*>(src);
+    copy_grid<4, Pair<cx<T>>>(Py, Nh >> 1, tid, nt, [&](int i, int, int) { return src2[i]; },
+                              [&](int, int y, int x2, Pair<cx<T>> v) {
+                                cx<T>* row = lds + y * ld;
+                                row[posx[2 * x2]] = v.a;
+                                row[posx[2 * x2 + 1]] = v.b;
+                              });
+  } else {
+    copy_grid<8, cx<T>>(Py, Nh, tid, nt, [&](int i, int, int) { return src[i]; },
+                        [&](int, int y, int x, cx<T> v) { lds[y * ld + posx[x]] = v; });
+  }
   bar();
   eng.template dit<-1, MAXR>(lds, Py, ld, 1, plx, twx, tid, nt, bar);
-  const int np = Nh / 2 + 1;
-  const FastDiv dnp = make_fastdiv((uint32_t)np);
-  for (int i = tid; i < Py * np; i += nt) {
-    const int y = (int)fdiv((uint32_t)i, dnp);
-    r2c_post(lds + y * ld, i - y * np, Nh, twr);
-  }
+  pair_pass_rows<true>(lds, Py, ld, Nh, twr, tid, nt);
   bar();
   eng.template dif<-1, MAXR>(lds, H, 1, ld, ply, twy, tid, nt, bar);
   cx<T>* dst = a.spec + f * a.slab + (bx.soff - a.sbias) + (int64_t)z * Py * H;
@@ -557,12 +569,7 @@ PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>*
   bar();
   eng.template dit<+1, MAXR>(lds, H, 1, ld, ply, twy, tid, nt, bar);
   const int ny = bx.n[1], gy = bx.g[1];
-  const int np = Nh / 2 + 1;
-  const FastDiv dnp = make_fastdiv((uint32_t)np);
-  for (int i = tid; i < ny * np; i += nt) {
-    const int y = (int)fdiv((uint32_t)i, dnp);
-    c2r_pre(lds + (gy + y) * ld, i - y * np, Nh, twr);
-  }
+  pair_pass_rows<false>(lds + gy * ld, ny, ld, Nh, twr, tid, nt);
   bar();
   eng.template dif<+1, MAXR>(lds + gy * ld, ny, ld, 1, plx, twx, tid, nt, bar);
   // 1/V applied in FP64 and rounded once: an FP32 1/V (not a power of two for
@@ -572,6 +579,27 @@ PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>*
   T* dst = a.out[f] + bx.foff + (int64_t)z * Py * Px;
   [[maybe_unused]] T* ldsT = reinterpret_cast<T*>(lds);
   constexpr bool push = PUSH;  // the fused E,B exchange (compiled only where used)
+  T* dst0 = dst + (int64_t)gy * Px + gx;  // first interior cell of the plane
+  if (!push && ((gx | nx) & 1) == 0 && (reinterpret_cast<uintptr_t>(dst0) % sizeof(Pair<T>)) == 0) {
+    // cells x, x+1 (x even) are the two halves of one complex LDS entry: one
+    // LDS read and one 2-wide access per pair
+    const int hx = gx >> 1;
+    copy_grid<8, Pair<T>>(ny, nx >> 1, tid, nt,
+                          [&](int, int yy, int x2) {
+                            const cx<T> v = lds[(gy + yy) * ld + posx[hx + x2]];
+                            return Pair<T>{(T)((double)v.x * sc), (T)((double)v.y * sc)};
+                          },
+                          [&](int, int yy, int x2, Pair<T> v) {
+                            Pair<T>* q = reinterpret_cast<Pair<T>*>(dst0 + (int64_t)yy * Px) + x2;
+                            if (INC) {  // v is the increment
+                              const Pair<T> o = *q;
+                              v.a = o.a + v.a;
+                              v.b = o.b + v.b;
+                            }
+                            *q = v;
+                          });
+    return;
+  }
   copy_grid<8, T>(ny, nx, tid, nt,
                   [&](int, int yy, int xi) {
                     const int x = gx + xi;
@@ -658,12 +686,7 @@ PSATD_HD void body_x_fwd(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>
                          });
   bar();
   eng.template dit<-1, MAXR>(lds, ny, ld, 1, plx, twx, tid, nt, bar);
-  const int np = Nh / 2 + 1;
-  const FastDiv dnp = make_fastdiv((uint32_t)np);
-  for (int i = tid; i < ny * np; i += nt) {
-    const int y = (int)fdiv((uint32_t)i, dnp);
-    r2c_post(lds + y * ld, i - y * np, Nh, twr);
-  }
+  pair_pass_rows<true>(lds, ny, ld, Nh, twr, tid, nt);
   bar();
   cx<T>* dst = a.spec + f * a.slab + (bx.soff - a.sbias) + ((int64_t)z * Py + y0) * H;
   const FastDiv dH = make_fastdiv((uint32_t)H);
@@ -773,12 +796,7 @@ PSATD_HD void body_x_inv(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>
                            }
                          });
   bar();
-  const int np = Nh / 2 + 1;
-  const FastDiv dnp = make_fastdiv((uint32_t)np);
-  for (int i = tid; i < ny * np; i += nt) {
-    const int y = (int)fdiv((uint32_t)i, dnp);
-    c2r_pre(lds + y * ld, i - y * np, Nh, twr);
-  }
+  pair_pass_rows<false>(lds, ny, ld, Nh, twr, tid, nt);
   bar();
   eng.template dif<+1, MAXR>(lds, ny, ld, 1, plx, twx, tid, nt, bar);
   const double sc = 1.0 / ((double)Px * (double)Py * (double)Pz);
