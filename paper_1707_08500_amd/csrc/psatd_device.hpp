@@ -98,9 +98,10 @@ PSATD_HD void copy_batched(int total, int tid, int nt, Src src, Dst dst) {
   }
 }
 
-// Two neighbouring values accessed as one aligned vector.
+// Two neighbouring values accessed as one vector (aligned to its size, at
+// most 16 bytes: the widest single access).
 template <typename V>
-struct alignas(2 * sizeof(V)) Pair {
+struct alignas(2 * sizeof(V) < 16 ? 2 * sizeof(V) : 16) Pair {
   V a, b;
 };
 
@@ -398,11 +399,25 @@ PSATD_HD void body_z_update(const UpdArgs<T>& a, int item, int tid, int nt, cx<T
   const cx<T>* src = a.spec + (bx.soff - a.sbias) + q0;
   const int64_t slab = a.slab;
   for (int i = tid; i < Pz; i += nt) twz[i] = gtz[i];
-  copy_grid3<8, cx<T>>(9, Pz, PB, tid, nt,
-      [&](int, int f, int z, int p) {
-        return (p < np) ? src[f * slab + (int64_t)z * nq + p] : cx<T>{T(0), T(0)};
-      },
-      [&](int, int f, int z, int p, cx<T> v) { lds[z * W + f * PB + p] = v; });
+  // a full tile whose pencil runs start at even offsets moves two neighbouring
+  // pencils per access
+  const bool pairs = (PB % 2) == 0 && np == PB &&
+                     (((int64_t)nq | slab | (int64_t)(bx.soff - a.sbias + q0)) & 1) == 0;
+  if (pairs) {
+    copy_grid3<4, Pair<cx<T>>>(9, Pz, PB / 2, tid, nt,
+        [&](int, int f, int z, int p2) {
+          return *reinterpret_cast<const Pair<cx<T>>*>(src + f * slab + (int64_t)z * nq + 2 * p2);
+        },
+        [&](int, int f, int z, int p2, Pair<cx<T>> v) {
+          *reinterpret_cast<Pair<cx<T>>*>(lds + z * W + f * PB + 2 * p2) = v;
+        });
+  } else {
+    copy_grid3<8, cx<T>>(9, Pz, PB, tid, nt,
+        [&](int, int f, int z, int p) {
+          return (p < np) ? src[f * slab + (int64_t)z * nq + p] : cx<T>{T(0), T(0)};
+        },
+        [&](int, int f, int z, int p, cx<T> v) { lds[z * W + f * PB + p] = v; });
+  }
   bar();
   eng.template dif<-1, MAXR>(lds, 9 * PB, 1, W, plz, twz, tid, nt, bar);
 
@@ -437,6 +452,16 @@ PSATD_HD void body_z_update(const UpdArgs<T>& a, int item, int tid, int nt, cx<T
   const int gz = bx.g[2];
   cx<T>* dst = a.spec + (bx.soff - a.sbias) + q0 + (int64_t)gz * nq;
   const cx<T>* res = lds + gz * W;
+  if (pairs) {
+    copy_grid3<4, Pair<cx<T>>>(6, bx.n[2], PB / 2, tid, nt,
+        [&](int, int f, int z, int p2) {
+          return *reinterpret_cast<const Pair<cx<T>>*>(res + z * W + f * PB + 2 * p2);
+        },
+        [&](int, int f, int z, int p2, Pair<cx<T>> v) {
+          *reinterpret_cast<Pair<cx<T>>*>(dst + f * slab + (int64_t)z * nq + 2 * p2) = v;
+        });
+    return;
+  }
   copy_grid3<8, cx<T>>(6, bx.n[2], PB, tid, nt,
                        [&](int, int f, int z, int p) { return res[z * W + f * PB + p]; },
                        [&](int, int f, int z, int p, cx<T> v) {
