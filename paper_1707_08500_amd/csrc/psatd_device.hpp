@@ -144,6 +144,58 @@ PSATD_HD void copy_grid(int R, int C, int tid, int nt, Get get, Put put) {
   }
 }
 
+// The same walk over the pairs (e, e+1), e = 2 j, of a row-major R x C grid
+// with R C even (a pair may straddle two rows): get(j, r0, c0, r1, c1) -> V,
+// put(j, r0, c0, r1, c1, v), with (r1, c1) the position of e + 1.
+template <int U, class V, class Get, class Put>
+PSATD_HD void copy_grid_pairs(int R, int C, int tid, int nt, Get get, Put put) {
+  const int total = (R * C) >> 1;
+  const FastDiv dC = make_fastdiv((uint32_t)C);
+  int r = (int)fdiv((uint32_t)(2 * tid), dC);
+  int c = 2 * tid - r * C;
+  const int dr = (int)fdiv((uint32_t)(2 * nt), dC);
+  const int dc = 2 * nt - dr * C;
+  auto advance = [&](int& rr, int& cc) {
+    cc += dc;
+    rr += dr;
+    if (cc >= C) {
+      cc -= C;
+      ++rr;
+    }
+  };
+  auto second = [&](int rr, int cc, int& r1, int& c1) {
+    const bool wrap = cc + 1 == C;
+    r1 = wrap ? rr + 1 : rr;
+    c1 = wrap ? 0 : cc + 1;
+  };
+  int j = tid;
+  for (; j + (U - 1) * nt < total; j += U * nt) {
+    V v[U];
+    int rs[U], cs[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      rs[u] = r;
+      cs[u] = c;
+      int r1, c1;
+      second(r, c, r1, c1);
+      v[u] = get(j + u * nt, r, c, r1, c1);
+      advance(r, c);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int r1, c1;
+      second(rs[u], cs[u], r1, c1);
+      put(j + u * nt, rs[u], cs[u], r1, c1, v[u]);
+    }
+  }
+  for (; j < total; j += nt) {
+    int r1, c1;
+    second(r, c, r1, c1);
+    put(j, r, c, r1, c1, get(j, r, c, r1, c1));
+    advance(r, c);
+  }
+}
+
 // The same walk over an A x B x C box (C fastest): get(i, a, b, c), put(i, a, b, c, v).
 template <int U, class V, class Get, class Put>
 PSATD_HD void copy_grid3(int A, int B, int C, int tid, int nt, Get get, Put put) {
@@ -589,8 +641,18 @@ PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>*
   const cx<T>* src = a.spec + f * a.slab + (bx.soff - a.sbias) + (int64_t)z * Py * H;
   for (int i = tid; i < Py + Nh + Px; i += nt)  // twy, twx, twr are contiguous
     twy[i] = i < Py ? gty[i] : (i < Py + Nh ? gtx[i - Py] : gtr[i - Py - Nh]);
-  copy_grid<8, cx<T>>(Py, H, tid, nt, [&](int i, int, int) { return src[i]; },
-                      [&](int, int ky, int kx, cx<T> v) { lds[posy[ky] * ld + kx] = v; });
+  // FP32: two spectrum entries per access (measured slower in FP64)
+  if (sizeof(T) == 4 && ((Py * H) & 1) == 0 && (reinterpret_cast<uintptr_t>(src) % sizeof(Pair<cx<T>>)) == 0) {
+    const Pair<cx<T>>* src2 = reinterpret_cast<const Pair<cx<T>>*>(src);
+    copy_grid_pairs<4, Pair<cx<T>>>(Py, H, tid, nt, [&](int j, int, int, int, int) { return src2[j]; },
+        [&](int, int r0, int c0, int r1, int c1, Pair<cx<T>> v) {
+          lds[posy[r0] * ld + c0] = v.a;
+          lds[posy[r1] * ld + c1] = v.b;
+        });
+  } else {
+    copy_grid<8, cx<T>>(Py, H, tid, nt, [&](int i, int, int) { return src[i]; },
+                        [&](int, int ky, int kx, cx<T> v) { lds[posy[ky] * ld + kx] = v; });
+  }
   bar();
   eng.template dit<+1, MAXR>(lds, H, 1, ld, ply, twy, tid, nt, bar);
   const int ny = bx.n[1], gy = bx.g[1];
@@ -605,6 +667,31 @@ PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>*
   [[maybe_unused]] T* ldsT = reinterpret_cast<T*>(lds);
   constexpr bool push = PUSH;  // the fused E,B exchange (compiled only where used)
   T* dst0 = dst + (int64_t)gy * Px + gx;  // first interior cell of the plane
+  if (!push && sizeof(T) == 4 && (gx & 1) == 0 && (nx & 3) == 0 && (Px & 3) == 0 &&
+      (reinterpret_cast<uintptr_t>(dst0) % sizeof(Pair<Pair<T>>)) == 0) {
+    // FP32: four cells (two complex LDS entries, 16 bytes) per access
+    const int hx = gx >> 1;
+    using Q = Pair<Pair<T>>;
+    copy_grid<4, Q>(ny, nx >> 2, tid, nt,
+                    [&](int, int yy, int x4) {
+                      const cx<T>* row = lds + (gy + yy) * ld;
+                      const cx<T> v0 = row[posx[hx + 2 * x4]], v1 = row[posx[hx + 2 * x4 + 1]];
+                      return Q{{(T)((double)v0.x * sc), (T)((double)v0.y * sc)},
+                               {(T)((double)v1.x * sc), (T)((double)v1.y * sc)}};
+                    },
+                    [&](int, int yy, int x4, Q v) {
+                      Q* q = reinterpret_cast<Q*>(dst0 + (int64_t)yy * Px) + x4;
+                      if (INC) {  // v is the increment
+                        const Q o = *q;
+                        v.a.a = o.a.a + v.a.a;
+                        v.a.b = o.a.b + v.a.b;
+                        v.b.a = o.b.a + v.b.a;
+                        v.b.b = o.b.b + v.b.b;
+                      }
+                      *q = v;
+                    });
+    return;
+  }
   if (!push && ((gx | nx) & 1) == 0 && (reinterpret_cast<uintptr_t>(dst0) % sizeof(Pair<T>)) == 0) {
     // cells x, x+1 (x even) are the two halves of one complex LDS entry: one
     // LDS read and one 2-wide access per pair
