@@ -38,6 +38,7 @@ struct HostTables {
   bool split = false;  // x/y pass split into x rows and y columns (large planes)
   std::vector<PushBlk> push;      // fused E,B exchange: guard pieces per source box
   std::vector<int32_t> push_off;  // nsub + 1
+  std::vector<FillPiece> fillp;   // guard fill: the pieces with offsets and pitches
   std::vector<int32_t> itemsG;    // guard fill: prefix over pieces of their z extent
   std::vector<int32_t> pieceOf;   // guard fill: item -> piece
   bool fuse_eb = false;           // E,B guards written by the inverse pass
@@ -329,6 +330,25 @@ inline void build_push(HostTables& h) {
           }
     }
     h.push_off[s + 1] = (int32_t)h.push.size();
+  }
+  // the pieces as the guard fill reads them
+  const int V = 16 / real_size(h.prec);  // elements per 16-byte access
+  h.fillp.clear();
+  for (const PushBlk& k : h.push) {
+    const BoxD& sb = h.box[k.src];
+    const BoxD& db = h.box[k.dst];
+    FillPiece f{};
+    f.sP0 = sb.P[0];
+    f.dP0 = db.P[0];
+    f.sPl = sb.P[0] * sb.P[1];
+    f.dPl = db.P[0] * db.P[1];
+    f.ly = k.ly;
+    f.lx = k.lx;
+    f.so = sb.foff + ((int64_t)(sb.g[2] + k.z0) * sb.P[1] + (sb.g[1] + k.y0)) * sb.P[0] + sb.g[0] + k.x0;
+    f.dof = db.foff + ((int64_t)k.qz * db.P[1] + k.qy) * db.P[0] + k.qx;
+    f.vec = (k.lx % V == 0 && f.so % V == 0 && f.dof % V == 0 && f.sP0 % V == 0 && f.dP0 % V == 0 &&
+             f.sPl % V == 0 && f.dPl % V == 0);
+    h.fillp.push_back(f);
   }
   // work list of the guard fill: one item per z-plane of every piece
   h.itemsG.assign(h.push.size() + 1, 0);

@@ -285,6 +285,7 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   const size_t o_push = reserve(std::max<size_t>(h.push.size(), 1) * sizeof(PushBlk));
   const size_t o_pof = reserve(h.push_off.size() * 4);
   const size_t o_iG = reserve(h.itemsG.size() * 4);
+  const size_t o_fp = reserve(std::max<size_t>(h.fillp.size(), 1) * sizeof(FillPiece));
   const size_t o_pOf = reserve(std::max<size_t>(h.pieceOf.size(), 1) * 4);
   std::vector<unsigned char> hb(total, 0);
   auto put = [&](size_t off, const void* src, size_t bytes) {
@@ -310,6 +311,7 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   put(o_push, h.push.data(), h.push.size() * sizeof(PushBlk));
   put(o_pof, h.push_off.data(), h.push_off.size() * 4);
   put(o_iG, h.itemsG.data(), h.itemsG.size() * 4);
+  put(o_fp, h.fillp.data(), h.fillp.size() * sizeof(FillPiece));
   put(o_pOf, h.pieceOf.data(), h.pieceOf.size() * 4);
   if ((e = hipMalloc(&p->blob, total)) != hipSuccess) return hipfail(e, "hipMalloc(tables)");
   if ((e = hipMemcpy(p->blob, hb.data(), total, hipMemcpyHostToDevice)) != hipSuccess)
@@ -361,6 +363,7 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   d.push = reinterpret_cast<const PushBlk*>(B + o_push);
   d.push_off = reinterpret_cast<const int32_t*>(B + o_pof);
   d.itemsG = reinterpret_cast<const int32_t*>(B + o_iG);
+  d.fillp = reinterpret_cast<const FillPiece*>(B + o_fp);
   d.pieceOf = reinterpret_cast<const int32_t*>(B + o_pOf);
   d.npiece = (int32_t)h.push.size();
   d.nG = h.itemsG.back();

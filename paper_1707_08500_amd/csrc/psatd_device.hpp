@@ -945,10 +945,21 @@ PSATD_HD void body_x_inv(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>
 
 // --------------------------------------------------------------- exchange
 
+// A guard piece as the fill reads it: the first cell of its first z-plane in
+// the owner's interior and in the destination's guard region, and the
+// pitches, worked out on the host (one load per work item instead of a chain
+// through the piece and both box descriptors).
+struct FillPiece {
+  int64_t so, dof;    // first cell (plane 0): owner, destination
+  int32_t sPl, dPl;   // plane pitches (elements)
+  int32_t sP0, dP0;   // row pitches (elements)
+  int32_t ly, lx;     // rows per plane, row length
+  int32_t vec, pad_;  // 16-byte accesses: offsets, pitches and lx multiples of 16 bytes
+};
+
 template <typename T>
 struct FillArgs {
-  const BoxD* box;
-  const PushBlk* piece;     // guard pieces (each guard cell in exactly one)
+  const FillPiece* piece;   // guard pieces (each guard cell in exactly one)
   const int32_t* items;     // prefix over pieces of lz
   const int32_t* piece_of;  // item -> piece
   int32_t ncomp;
@@ -969,16 +980,13 @@ struct alignas(16) Vec16 {
 template <typename T>
 PSATD_HD void body_fill(const FillArgs<T>& a, int item, int tid, int nt) {
   const int b = a.piece_of[item];
-  const PushBlk k = a.piece[b];
+  const FillPiece k = a.piece[b];
   const int zi = item - a.items[b];
-  const BoxD& sb = a.box[k.src];
-  const BoxD& db = a.box[k.dst];
-  const int sP0 = sb.P[0], dP0 = db.P[0];
-  const int64_t so = sb.foff + ((int64_t)(sb.g[2] + k.z0 + zi) * sb.P[1] + (sb.g[1] + k.y0)) * sP0 +
-                     sb.g[0] + k.x0;
-  const int64_t dof = db.foff + ((int64_t)(k.qz + zi) * db.P[1] + k.qy) * dP0 + k.qx;
+  const int sP0 = k.sP0, dP0 = k.dP0;
+  const int64_t so = k.so + (int64_t)zi * k.sPl;
+  const int64_t dof = k.dof + (int64_t)zi * k.dPl;
   constexpr int V = 16 / (int)sizeof(T);
-  const bool vec = (k.lx % V) == 0 && (so % V) == 0 && (dof % V) == 0 && (sP0 % V) == 0 && (dP0 % V) == 0;
+  const bool vec = k.vec != 0;
   const int W = vec ? V : 1;  // elements per access
   const int lw = k.lx / W;
   const int n = k.ly * lw;

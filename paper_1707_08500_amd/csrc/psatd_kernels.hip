@@ -235,8 +235,7 @@ hipError_t prepare_kernels(bool f64, int spl, int ldsF, int ldsI, int ldsU, int 
 template <typename T>
 static hipError_t fill_t(const DevPlan& p, void* const* comps, int ncomp, hipStream_t st) {
   FillArgs<T> a;
-  a.box = p.box;
-  a.piece = p.push;
+  a.piece = p.fillp;
   a.items = p.itemsG;
   a.piece_of = p.pieceOf;
   a.ncomp = ncomp;

@@ -32,6 +32,7 @@ struct DevPlan {
   int32_t ldsX, ldsY;
   int32_t split;
   const PushBlk* push;       // guard pieces (guard fill, fused E,B exchange)
+  const FillPiece* fillp;    // guard fill: pieces with offsets and pitches
   const int32_t* itemsG;     // guard fill: prefix over pieces of their z extent
   const int32_t* pieceOf;    // guard fill: item -> piece
   int32_t npiece, nG;
