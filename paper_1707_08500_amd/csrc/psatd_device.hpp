@@ -364,24 +364,28 @@ PSATD_HD void psatd_point(T* vr, T* vi /* E0 E1 E2 B0 B1 B2 J0 J1 J2 */, double 
   const double k2 = kx * kx + ky * ky + kz * kz;
   double C, Sck, X1, X2;
   const double c2 = c * c;
+  const double rc = 1.0 / c;  // uniform: hoisted out of the k-point loop
   if (k2 == 0.0) {
     C = INC ? 0.0 : 1.0;
     Sck = dt;
     X1 = 0.5 * c2 * dt * dt;
     X2 = -c2 * dt * dt * dt / 6.0;
   } else {
+    // one sincos and one division (1/k) per k-point; the rest are products
     const double k = sqrt(k2);
+    const double rk = 1.0 / k, rk2 = rk * rk;
     const double th = c * k * dt;
-    const double sh = sin(0.5 * th), ch = cos(0.5 * th);
+    double sh, ch;
+    sincos(0.5 * th, &sh, &ch);
     C = INC ? -2.0 * sh * sh : 1.0 - 2.0 * sh * sh;
-    Sck = (2.0 * sh * ch) / (c * k);
-    X1 = 2.0 * sh * sh / k2;
+    Sck = (2.0 * sh * ch) * rk * rc;
+    X1 = 2.0 * sh * sh * rk2;
     const double t2 = th * th;
     if (t2 < 1e-2) {
       X2 = -c2 * dt * dt * dt *
            (1.0 / 6.0 - t2 * (1.0 / 120.0 - t2 * (1.0 / 5040.0 - t2 * (1.0 / 362880.0 - t2 / 39916800.0))));
     } else {
-      X2 = (Sck - dt) / k2;
+      X2 = (Sck - dt) * rk2;
     }
   }
   // The coefficients are FP64; the multiply-adds run in the state's type T
@@ -397,7 +401,7 @@ PSATD_HD void psatd_point(T* vr, T* vi /* E0 E1 E2 B0 B1 B2 J0 J1 J2 */, double 
   const T K[3] = {tkx, tky, tkz};
   const T tC = (T)C, tS = (T)Sck, tX1 = (T)X1, tX2 = (T)X2;
   const T a1 = (T)(c2 * Sck);
-  const T x1c = (T)(X1 / c2);
+  const T x1c = (T)(X1 * (rc * rc));
   const T kEr = tkx * er[0] + tky * er[1] + tkz * er[2];
   const T kEi = tkx * ei[0] + tky * ei[1] + tkz * ei[2];
   const T kJr = tkx * jr[0] + tky * jr[1] + tkz * jr[2];
