@@ -7,6 +7,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "fft_engine.hpp"
 
 namespace psatd {
@@ -358,7 +360,9 @@ struct UpdConst {
 // C - 1 = -2 sin^2(th/2), exact without cancellation).  The FP32 path moves the
 // increment through the FFTs: for resolved fields it is far smaller than E,
 // so the FFT roundoff, relative to what is transformed, shrinks with it.
-template <typename T, bool INC = false>
+// JOINT_SINCOS: one sincos call (fewer instructions) or sin and cos as two
+// calls (fewer live registers: the matrix-core z tiles keep two tiles per CU).
+template <typename T, bool INC = false, bool JOINT_SINCOS = true>
 PSATD_HD void psatd_point(T* vr, T* vi /* E0 E1 E2 B0 B1 B2 J0 J1 J2 */, double kx, double ky,
                           double kz, double c, double dt) {
   const double k2 = kx * kx + ky * ky + kz * kz;
@@ -371,12 +375,17 @@ PSATD_HD void psatd_point(T* vr, T* vi /* E0 E1 E2 B0 B1 B2 J0 J1 J2 */, double 
     X1 = 0.5 * c2 * dt * dt;
     X2 = -c2 * dt * dt * dt / 6.0;
   } else {
-    // one sincos and one division (1/k) per k-point; the rest are products
+    // one division (1/k) per k-point; the rest are products
     const double k = sqrt(k2);
     const double rk = 1.0 / k, rk2 = rk * rk;
     const double th = c * k * dt;
     double sh, ch;
-    sincos(0.5 * th, &sh, &ch);
+    if (JOINT_SINCOS) {
+      sincos(0.5 * th, &sh, &ch);
+    } else {
+      sh = sin(0.5 * th);
+      ch = cos(0.5 * th);
+    }
     C = INC ? -2.0 * sh * sh : 1.0 - 2.0 * sh * sh;
     Sck = (2.0 * sh * ch) * rk * rc;
     X1 = 2.0 * sh * sh * rk2;
@@ -496,7 +505,8 @@ PSATD_HD void body_z_update(const UpdArgs<T>& a, int item, int tid, int nt, cx<T
     const int q = q0 + p;
     const int ky = (int)fdiv((uint32_t)q, dH);
     const int kx = q - ky * H;
-    psatd_point<T, INC>(vr, vi, kxt[kx], kyt[ky], kzt[kzi[slot]], a.k.c, a.k.dt);
+    psatd_point<T, INC, std::is_same<Eng, FftValu>::value>(vr, vi, kxt[kx], kyt[ky], kzt[kzi[slot]], a.k.c,
+                                                           a.k.dt);
 #pragma unroll
     for (int f = 0; f < 6; ++f) row[f * PB] = cx<T>{vr[f], vi[f]};
   }
