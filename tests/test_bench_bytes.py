@@ -1,0 +1,62 @@
+"""CPU: the algorithmic bytes bench.py divides by the measured kernel time
+(roofline.achieved), checked against a count made by hand for the 256^3 grid
+cut into 4x4x4 boxes of 64^3 with 16 guard cells (padded 96^3, H = 49)."""
+import os
+import sys
+
+import numpy as np
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import bench  # noqa: E402
+from paper_1707_08500_amd import synth  # noqa: E402
+
+
+class FakePlan:
+    """The three things algorithmic_bytes asks a plan: layout, tuning, precision."""
+
+    def __init__(self, padded, precision, fuse=0):
+        self.padded = padded
+        self.precision = precision
+        self.fuse = fuse
+
+    def layout(self, s):
+        return tuple(self.padded[s]), 0
+
+    def tuning(self):
+        return {"fuse_eb": self.fuse}
+
+
+def cfg2():
+    lo, n, g = synth.uniform_decomposition((256, 256, 256), (4, 4, 4), 16)
+    padded = [tuple(int(v) for v in np.asarray(n[s]) + 2 * np.asarray(g[s])) for s in range(len(lo))]
+    return lo, n, g, padded
+
+
+def test_config2_bytes_fp32_increment_form():
+    lo, n, g, padded = cfg2()
+    assert len(lo) == 64 and set(padded) == {(96, 96, 96)}
+    out, kpoints = bench.algorithmic_bytes(FakePlan(padded, "f32"), lo, n, g, 4)
+    P, I, H, boxes = 96, 64, 49, 64
+    guard = P ** 3 - I ** 3                        # 622592 guard cells per box
+    assert kpoints == boxes * P * P * H
+    # J and E,B exchange: every guard cell read once and written once
+    assert out["exchange_J"] == boxes * guard * 3 * 2 * 4
+    assert out["exchange_EB"] == boxes * guard * 6 * 2 * 4
+    # forward x/y: 9 padded real fields read, 9 half spectra written
+    assert out["fft_xy_fwd"] == boxes * (9 * P ** 3 * 4 + 9 * P * P * H * 8)
+    # z pass: 9 complex read at every k-point, 6 written on the 64 interior z-planes
+    assert out["z_update"] == boxes * (9 * P + 6 * I) * P * H * 8
+    assert out["z_update"] == 3005743104
+    # inverse: 6 half spectra of the interior planes read; the increment is added
+    # to the interior cells (read and written)
+    assert out["fft_xy_inv"] == boxes * (6 * I * P * H * 8 + 2 * 6 * I ** 3 * 4)
+
+
+def test_fp64_writes_without_reading_and_fused_exchange_moves_nothing():
+    lo, n, g, padded = cfg2()
+    out, _ = bench.algorithmic_bytes(FakePlan(padded, "f64"), lo, n, g, 8)
+    P, I, H, boxes = 96, 64, 49, 64
+    assert out["fft_xy_inv"] == boxes * (6 * I * P * H * 16 + 6 * I ** 3 * 8)
+    fused, _ = bench.algorithmic_bytes(FakePlan(padded, "f64", fuse=1), lo, n, g, 8)
+    assert fused["exchange_EB"] == 0
+    assert fused["fft_xy_inv"] == out["fft_xy_inv"] + boxes * (P ** 3 - I ** 3) * 6 * 8
