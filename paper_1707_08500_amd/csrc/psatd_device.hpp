@@ -321,16 +321,14 @@ PSATD_HD void body_fwd_xy(const FwdArgs<T>& a, int item, int tid, int nt, cx<T>*
   for (int i = tid; i < Nh + Py + Px; i += nt)  // twx, twy, twr are contiguous
     twx[i] = i < Nh ? gtx[i] : (i < Nh + Py ? gty[i - Nh] : gtr[i - Nh - Py]);
   if ((Nh & 1) == 0 && (reinterpret_cast<uintptr_t>(src) % sizeof(Pair<cx<T>>)) == 0) {
-    // two neighbouring complex values per access (rows of even length); FP32
-    // keeps 8 pairs in flight per thread, FP64 4 (measured)
+    // two neighbouring complex values per access (rows of even length)
     const Pair<cx<T>>* src2 = reinterpret_cast<const Pair<cx<T>>*>(src);
-    constexpr int UP = sizeof(T) == 4 ? 8 : 4;
-    copy_grid<UP, Pair<cx<T>>>(Py, Nh >> 1, tid, nt, [&](int i, int, int) { return src2[i]; },
-                               [&](int, int y, int x2, Pair<cx<T>> v) {
-                                 cx<T>* row = lds + y * ld;
-                                 row[posx[2 * x2]] = v.a;
-                                 row[posx[2 * x2 + 1]] = v.b;
-                               });
+    copy_grid<4, Pair<cx<T>>>(Py, Nh >> 1, tid, nt, [&](int i, int, int) { return src2[i]; },
+                              [&](int, int y, int x2, Pair<cx<T>> v) {
+                                cx<T>* row = lds + y * ld;
+                                row[posx[2 * x2]] = v.a;
+                                row[posx[2 * x2 + 1]] = v.b;
+                              });
   } else {
     copy_grid<8, cx<T>>(Py, Nh, tid, nt, [&](int i, int, int) { return src[i]; },
                         [&](int, int y, int x, cx<T> v) { lds[y * ld + posx[x]] = v; });
