@@ -20,7 +20,9 @@ scalability for electromagnetic PIC simulations of plasmas"):
                           form).
 * ``step_global``     -- one PSATD step on a periodic grid: forward FFT, update,
                           inverse FFT ("O-global", the PSATD-global method of
-                          Sec. 3.2 / Fig. 2b, as mathematics, not distributed).
+                          Sec. 3.2 / Fig. 2b, as mathematics, not distributed);
+                          real-to-complex transforms over the half spectrum,
+                          the pointwise update spread over threads by kz slab.
 * ``Decomposition``, ``scatter``, ``gather``, ``exchange_fill``,
   ``exchange_sum``, ``step_local`` -- the domain-decomposed method of Sec. 3.2
                           (Fig. 2a and the three steps of Fig. 3): every
@@ -202,18 +204,76 @@ def ifft3(F):
     return sfft.ifftn(F, axes=(-3, -2, -1), workers=_WORKERS)
 
 
+def rfft3(f):
+    """Unnormalised forward 3D FFT of a real array over the last three axes,
+    kept on the half spectrum kx = 0..Nx//2 (library routine; the other half is
+    the complex conjugate of this one)."""
+    return sfft.rfftn(f, axes=(-3, -2, -1), workers=_WORKERS)
+
+
+def irfft3(F, shape_zyx):
+    """Inverse of :func:`rfft3` onto a real (..., Nz, Ny, Nx) array, 1/N
+    included (library routine)."""
+    return sfft.irfftn(F, s=tuple(shape_zyx), axes=(-3, -2, -1), workers=_WORKERS)
+
+
+def k_grid_half(shape_zyx, d_xyz, p):
+    """:func:`k_grid` restricted to the half spectrum kx = 0..Nx//2 of rfft3."""
+    kx, ky, kz = k_grid(shape_zyx, d_xyz, p)
+    return kx[..., : shape_zyx[2] // 2 + 1], ky, kz
+
+
+_POOL = None
+
+
+def psatd_update_by_kz(Ek, Bk, Jk, kvec, c, dt):
+    """:func:`psatd_update` applied to slabs of consecutive kz planes by a pool
+    of threads.  The update acts on every k-point by itself (Eqs. PSATD_1 /
+    PSATD_2 couple the fields at one k only), so each point gets exactly the
+    arithmetic of one call on the whole spectrum; the slabs only bound the
+    size of numpy's temporaries and let the threads share the work."""
+    global _POOL
+    if _POOL is None:
+        from concurrent.futures import ThreadPoolExecutor
+        _POOL = ThreadPoolExecutor(max_workers=_WORKERS)
+    kx, ky, kz = kvec
+    Nz = Ek.shape[-3]
+    En = np.empty(np.broadcast_shapes(Ek.shape, Bk.shape, Jk.shape), dtype=np.complex128)
+    Bn = np.empty_like(En)
+    edges = np.linspace(0, Nz, min(Nz, 4 * _WORKERS) + 1).astype(int)
+
+    def slab(i):
+        z0, z1 = edges[i], edges[i + 1]
+        e, b = psatd_update(Ek[..., z0:z1, :, :], Bk[..., z0:z1, :, :], Jk[..., z0:z1, :, :],
+                            (kx, ky, kz[z0:z1]), c, dt)
+        En[..., z0:z1, :, :] = e
+        Bn[..., z0:z1, :, :] = b
+
+    list(_POOL.map(slab, range(len(edges) - 1)))
+    return En, Bn
+
+
 def step_global(E, B, J, d, p, c, dt, return_residue=False):
     """One PSATD step on a periodic box (Sec. 3.1): FFT E, B, J; update; inverse
-    FFT.  E, B, J are real (3, Nz, Ny, Nx) arrays; d = (dx, dy, dz)."""
+    FFT.  E, B, J are real (3, Nz, Ny, Nx) arrays; d = (dx, dy, dz).
+
+    The fields are real, so the transforms are taken real-to-complex over the
+    half spectrum kx = 0..Nx//2 (the update maps conjugate k-points to
+    conjugate values because [k](-m) = -[k](m) and the Nyquist entries are 0;
+    the other half adds nothing).  return_residue=True takes the full complex
+    transforms instead and also returns the largest imaginary part left by the
+    inverse, the check that the update keeps real fields real."""
     shape = E.shape[1:]
-    kvec = k_grid(shape, d, p)
-    En, Bn = psatd_update(fft3(E), fft3(B), fft3(J), kvec, c, dt)
-    e = ifft3(En)
-    b = ifft3(Bn)
     if return_residue:
+        kvec = k_grid(shape, d, p)
+        En, Bn = psatd_update(fft3(E), fft3(B), fft3(J), kvec, c, dt)
+        e = ifft3(En)
+        b = ifft3(Bn)
         res = max(np.abs(e.imag).max(), np.abs(b.imag).max())
         return e.real.copy(), b.real.copy(), res
-    return e.real.copy(), b.real.copy()
+    kvec = k_grid_half(shape, d, p)
+    En, Bn = psatd_update_by_kz(rfft3(E), rfft3(B), rfft3(J), kvec, c, dt)
+    return irfft3(En, shape), irfft3(Bn, shape)
 
 
 def run_global(E, B, J, d, p, c, dt, nsteps):

@@ -42,6 +42,20 @@ def test_P1_fft_matches_naive_dft(shape):
     assert np.abs(back - f).max() <= 1e-13 * np.abs(f).max()
 
 
+@pytest.mark.parametrize("shape", [(6, 5, 4), (7, 3, 11), (2, 9, 8), (5, 4, 7)])
+def test_P1_real_fft_matches_naive_dft_half_spectrum(shape):
+    """rfft3 is the kx = 0..Nx//2 half of the naive DFT of a real array (even
+    and odd Nx); irfft3 inverts it onto the real grid."""
+    r = np.random.default_rng(2)
+    f = r.normal(size=(2,) + shape)
+    ref = naive_dft3(f)[..., : shape[2] // 2 + 1]
+    got = O.rfft3(f)
+    assert got.shape == ref.shape
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    back = O.irfft3(got, shape)
+    assert np.abs(back - f).max() <= 1e-13 * np.abs(f).max()
+
+
 # ------------------------------------------------------- P2: order-p weights
 def test_P2_weights_textbook_golden():
     with open(os.path.join(GOLDEN, "fd_weights_textbook.txt")) as fh:
@@ -266,11 +280,18 @@ def test_P8_longitudinal_E():
     assert np.abs(O.div_spectral(En0, d, p) - O.div_spectral(E, d, p)).max() <= 1e-12 * np.abs(O.fft3(E)).max()
 
 
-def test_P12_imaginary_residue_small():
-    shape, d, p, c, dt = (9, 10, 12), (1.0, 1.0, 1.0), 0, 1.0, 0.5
+@pytest.mark.parametrize("shape,p", [((9, 10, 12), 0), ((8, 7, 9), 6), ((6, 6, 10), 2)])
+def test_P12_imaginary_residue_small_and_half_spectrum_step(shape, p):
+    """The full complex transforms leave only a rounding-level imaginary part
+    (the update keeps real fields real), and the default half-spectrum step
+    gives the same fields (even and odd Nx)."""
+    d, c, dt = (1.0, 1.1, 0.9), 1.3, 0.5
     E, B, J = random_state(shape, 41, d=d, p=p)
-    _, _, res = O.step_global(E, B, J, d, p, c, dt, return_residue=True)
+    e_c, b_c, res = O.step_global(E, B, J, d, p, c, dt, return_residue=True)
     assert res <= 1e-14 * max(np.abs(E).max(), 1.0) * 10
+    e_r, b_r = O.step_global(E, B, J, d, p, c, dt)
+    assert np.abs(e_r - e_c).max() <= 1e-14 * np.abs(e_c).max()
+    assert np.abs(b_r - b_c).max() <= 1e-14 * np.abs(b_c).max()
 
 
 # ------------------------------------------------------- P9: reductions
