@@ -336,7 +336,8 @@ def scatter(F, dec):
     out = []
     for s in range(dec.nsub):
         ix, iy, iz = dec.global_index(s)
-        out.append(F[..., iz[:, None, None], iy[None, :, None], ix[None, None, :]].copy())
+        # padded cell (z, y, x) <- F[..., iz[z], iy[y], ix[x]]: one gather per axis
+        out.append(F.take(iz, axis=-3).take(iy, axis=-2).take(ix, axis=-1))
     return out
 
 

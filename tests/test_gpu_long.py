@@ -1,0 +1,227 @@
+"""GPU parity over the configurations' own horizons: the HIP path through the
+C-ABI against the FP64 decomposed oracle (Sec. 3.2, Fig. 3, with the update of
+Eqs. PSATD_1/2 of Sec. 3.1), every field component gated by itself.
+
+* 96^3 local shape (the configuration-2/3 boxes: 64^3 + 16 guards, p = 32) on a
+  128x64x64 grid of 2x1x1 boxes, the configuration-2 input recipe, 100 steps;
+* 176^3 local shape (the configuration-5 boxes: 128^3 + 24 guards, p = 100) as
+  one box of a 128^3 grid whose guards wrap onto itself, three crossed
+  laser-like pulses plus Gaussian currents, 100 and 200 steps;
+* uneven boxes with the configuration-4 recipe (edges from {48, 64, 80, 96},
+  guards from {8, 16, 32}, p = 64) on a 144x144x96 grid, 40 steps.
+
+Every precision form starts from the same input, rounded to FP32 first, and
+is compared with one FP64 oracle run of that input.  Bars, per component
+(relative L2 over the global interior): FP64 <= 1e-12; FP32 VALU and the
+6-product split-BF16 form <= 1e-5; the 3-product form is reported and held
+to the bound its arithmetic gives (two BF16 terms per operand leave about
+5 * 2^-18 of relative error per matrix-core product).
+
+Per-component errors are printed and, when a gpurun_out/ folder exists at the
+repository root, appended to gpurun_out/long_parity.jsonl.
+"""
+import json
+import os
+import time
+
+import numpy as np
+import pytest
+
+from oracle import psatd_oracle as O
+from paper_1707_08500_amd import synth
+
+from psatd_cases import GpuCase, config2_fields, say
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+OUT = os.path.join(ROOT, "gpurun_out")
+NAMES = ("Ex", "Ey", "Ez", "Bx", "By", "Bz")
+FORMS = ("f64", "f32", "bf16x6", "bf16x3")
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16x6": 1e-5, "bf16x3": 1e-3}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1707_08500_amd import psatd  # noqa: F401  (raises if the library is missing)
+    yield
+
+
+def record(row):
+    say("  " + json.dumps(row))
+    if os.path.isdir(OUT):
+        with open(os.path.join(OUT, "long_parity.jsonl"), "a") as f:
+            f.write(json.dumps(row) + "\n")
+
+
+def f32_exact(*xs):
+    return [x.astype(np.float32).astype(np.float64) for x in xs]
+
+
+# ------------------------------------------------------------------ inputs
+def local96_case():
+    N = (128, 64, 64)
+    d = (1.0, 1.0, 1.0)
+    lo, n, g = synth.uniform_decomposition(N, (2, 1, 1), 16)
+    E, B, J = f32_exact(*config2_fields(N, d, 32))
+    return dict(N=N, d=d, lo=lo, n=n, g=g, p=32, dt=0.5, c=1.0, E=E, B=B, J=J)
+
+
+def crossed_pulses(N, d, c=1.0, wavelength=32.0, width=24.0):
+    """Three laser-like pulses (the configuration-5 profile): along +x with
+    (E_y, B_z), along +y with (E_z, B_x), along +z with (E_x, B_y); each is
+    uniform across its direction, so divergence-free for every order p."""
+    E = np.zeros((3, N[2], N[1], N[0]))
+    B = np.zeros_like(E)
+    for axis in range(3):
+        L = N[axis] * d[axis]
+        s = np.arange(N[axis]) * d[axis]
+        xc = 0.5 * L
+        prof = np.cos(2 * np.pi * (s - xc) / wavelength) * np.exp(-(s - xc) ** 2 / (2 * width ** 2))
+        shape = [1, 1, 1]
+        shape[2 - axis] = N[axis]  # arrays are [z][y][x]
+        prof = prof.reshape(shape)
+        e_comp, b_comp = (axis + 1) % 3, (axis + 2) % 3
+        E[e_comp] += prof
+        B[b_comp] += prof / c
+    return E, B
+
+
+def local176_case():
+    N = (128, 128, 128)
+    d = (1.0, 1.0, 1.0)
+    lo, n, g = synth.uniform_decomposition(N, (1, 1, 1), 24)
+    E, B = crossed_pulses(N, d)
+    J = synth.current_pulses(N, d, case=5, count=4, sigma=8.0, amp_range=(0.0, 0.1))
+    E, B, J = f32_exact(E, B, J)
+    return dict(N=N, d=d, lo=lo, n=n, g=g, p=100, dt=0.5, c=1.0, E=E, B=B, J=J)
+
+
+def uneven_case():
+    N = (144, 144, 96)
+    d = (1.0, 1.0, 1.0)
+    p = 64
+    lo, n, g = synth.uneven_decomposition(N, case=4)
+    J = synth.current_pulses(N, d, case=4, count=1, sigma=8.0)
+    ms, amps, phases = synth.wave_parameters(case=4, count=8, mmax=8)
+    E = np.zeros((3, N[2], N[1], N[0]))
+    B = np.zeros_like(E)
+    for m, a, ph in zip(ms, amps, phases):
+        kv = np.array([O.modified_k(N[u], d[u], p)[m[u] % N[u]] for u in range(3)])
+        a = O.project_transverse(a, kv)
+        a = 0.1 * a / np.linalg.norm(a)
+        kh = kv / np.linalg.norm(kv)
+        E += synth.plane_wave(N, m, a, ph)
+        B += synth.plane_wave(N, m, np.cross(kh, a), ph)
+    E, B, J = f32_exact(E, B, J)
+    return dict(N=N, d=d, lo=lo, n=n, g=g, p=p, dt=0.5, c=1.0, E=E, B=B, J=J)
+
+
+# --------------------------------------------------- runs, cached per module
+_STATE = {}
+
+
+def oracle_at(name, build, steps):
+    """O-local state (E, B boxes) of case `name` after `steps` steps; later
+    calls continue from the last cached step."""
+    st = _STATE.setdefault(name, {})
+    if "case" not in st:
+        st["case"] = build()
+    cs = st["case"]
+    if "oracle" not in st:
+        dec = O.Decomposition(cs["N"], cs["lo"], cs["n"], cs["g"])
+        st["dec"] = dec
+        st["oracle"] = (0, O.scatter(cs["E"], dec), O.scatter(cs["B"], dec), O.scatter(cs["J"], dec))
+    done, Eb, Bb, Jb = st["oracle"]
+    assert steps >= done
+    t0 = time.perf_counter()
+    chunk = 10
+    while done < steps:
+        k = min(chunk, steps - done)
+        Eb, Bb, Jb = O.run_local(Eb, Bb, Jb, st["dec"], cs["d"], cs["p"], cs["c"], cs["dt"], k)
+        done += k
+        say(f"  oracle {name}: step {done}/{steps} ({time.perf_counter() - t0:.1f} s)")
+    st["oracle"] = (done, Eb, Bb, Jb)
+    return O.gather(Eb, st["dec"]), O.gather(Bb, st["dec"])
+
+
+def gpu_at(name, build, form, steps):
+    """The GPU state of one precision form after `steps` steps, gathered to
+    the global grid; later calls continue the same buffers."""
+    st = _STATE.setdefault(name, {})
+    if "case" not in st:
+        st["case"] = build()
+    cs = st["case"]
+    runs = st.setdefault("gpu", {})
+    if form not in runs:
+        runs[form] = [0, GpuCase(cs["N"], cs["lo"], cs["n"], cs["g"], cs["p"], cs["dt"], cs["c"], form,
+                                 "replicated", cs["E"], cs["B"], cs["J"], d=cs["d"])]
+    done, gc = runs[form]
+    assert steps >= done
+    if steps > done:
+        gc.plan.run(gc.E, gc.B, gc.J, steps - done)
+        gc.plan.sync()
+        runs[form][0] = steps
+    return gc.gathered(gc.E), gc.gathered(gc.B)
+
+
+def compare(name, build, steps, forms=FORMS):
+    oE, oB = oracle_at(name, build, steps)
+    worst = {}
+    for form in forms:
+        gE, gB = gpu_at(name, build, form, steps)
+        err = [O.rel_l2(gE[a], oE[a]) for a in range(3)] + [O.rel_l2(gB[a], oB[a]) for a in range(3)]
+        num = float(np.sum((gE - oE) ** 2) + np.sum((gB - oB) ** 2))
+        den = float(np.sum(oE ** 2) + np.sum(oB ** 2))
+        record(dict(case=name, form=form, steps=steps, rel_l2=dict(zip(NAMES, err)),
+                    energy_norm=float(np.sqrt(num / den)), tol=TOL[form]))
+        worst[form] = max(err)
+    for form in forms:
+        assert worst[form] <= TOL[form], (form, worst[form])
+
+
+def drop(name):
+    st = _STATE.pop(name, {})
+    for _, gc in st.get("gpu", {}).values():
+        gc.plan.close()
+    import torch
+    torch.cuda.empty_cache()
+
+
+# ------------------------------------------------------------------- tests
+@pytest.mark.timeout(900)
+def test_local96_100_steps_all_forms_vs_oracle():
+    """Configurations 2 and 3: the 96^3 local shape (p = 32) and input recipe,
+    100 steps, all four precision forms against one FP64 oracle run."""
+    say("96^3 local shape (128x64x64 grid, 2x1x1 boxes, g=16, p=32), 100 steps")
+    compare("local96", local96_case, 100)
+    drop("local96")
+
+
+@pytest.mark.timeout(900)
+def test_local176_100_steps_all_forms_vs_oracle():
+    """Configuration 5's local shape and order (176^3 = 16 x 11 boxes,
+    p = 100), first half of its 200 steps, all four precision forms."""
+    say("176^3 local shape (128^3 grid, one box wrapping onto itself, g=24, p=100), 100 steps")
+    compare("local176", local176_case, 100)
+
+
+@pytest.mark.timeout(900)
+def test_local176_200_steps_all_forms_vs_oracle():
+    """The same runs continued to configuration 5's 200 steps."""
+    say("176^3 local shape, continued to 200 steps")
+    compare("local176", local176_case, 200)
+    drop("local176")
+
+
+@pytest.mark.timeout(900)
+def test_uneven_config4_recipe_40_steps_vs_oracle():
+    """Configuration 4's recipe on a reduced grid: 8 uneven boxes with 8
+    distinct padded shapes, every edge length and guard width of the recipe,
+    all boxes in one launch per phase, 40 steps."""
+    say("uneven boxes, 144x144x96 grid, p=64, 40 steps")
+    compare("uneven", uneven_case, 40, forms=("f64", "f32", "bf16x6"))
+    drop("uneven")
