@@ -62,11 +62,15 @@ typedef enum {
 
 typedef enum {
   PSATD_F64 = 0,        /* FP64 state, FP64 FFT, FP64 update */
-  PSATD_F32_VALU = 1,   /* FP32 state and FFT (vector ALU), FP64 coefficients and update */
-  /* FP32 state; the first (radix-16) stage of every transform whose length is a
-     multiple of 16 is a complex 16x16 DFT-GEMM on the matrix cores with the FP32
-     operands split into BF16 terms and FP32 accumulation; the other stages as
-     F32_VALU; FP64 coefficients and update. */
+  /* FP32 state and FFT (vector ALU).  The Sec. 3.1 coefficient tables are
+     evaluated in FP64; the update's multiply-adds run in FP32 on the
+     increments E' - E and B' - B, which the inverse FFT carries back and adds
+     to the state. */
+  PSATD_F32_VALU = 1,
+  /* FP32 state as PSATD_F32_VALU; in addition the first (radix-16) stage of
+     every transform whose length is a multiple of 16 is a complex 16x16
+     DFT-GEMM on the matrix cores with the FP32 operands split into BF16 terms
+     and FP32 accumulation; the other stages run on the vector ALU. */
   PSATD_F32_BF16X3 = 2, /* 2 terms per operand, 3 products (hi*hi + hi*lo + lo*hi) */
   PSATD_F32_BF16X6 = 3  /* 3 terms per operand, the 6 products of term order <= 2 */
 } psatd_precision;
@@ -163,8 +167,10 @@ psatd_status psatd_workspace_bytes(psatd_plan_t plan, int64_t* bytes);
 psatd_status psatd_set_workspace(psatd_plan_t plan, void* dev, int64_t bytes);
 
 /*
- * psatd_step -- one step (exchange_J, local push of every padded box, exchange_EB),
- * enqueued on the plan's stream.  E, B, J: arrays of 3 device field buffers.  The
+ * psatd_step -- one step of the domain-decomposed method of Sec. 3.2 (the three
+ * steps of Fig. 3: currents made consistent over the guard copies, every padded
+ * box advanced by its own local FFT push of Sec. 3.1, guard cells of E and B
+ * replaced by the owners' values), enqueued on the plan's stream.  E, B, J: arrays of 3 device field buffers.  The
  * state must be consistent on entry (every guard copy equal to its owner, as
  * psatd_scatter leaves it); it is consistent again on exit.  In PSATD_J_DEPOSITED mode
  * every call takes J as freshly deposited partial currents and sums them (after the
@@ -173,7 +179,8 @@ psatd_status psatd_set_workspace(psatd_plan_t plan, void* dev, int64_t bytes);
 psatd_status psatd_step(psatd_plan_t plan, void* const E[3], void* const B[3], void* const J[3]);
 
 /*
- * psatd_run -- nsteps >= 0 steps with J unchanged, replayed from a captured HIP graph
+ * psatd_run -- nsteps >= 0 steps of Sec. 3.2 / Fig. 3 with J unchanged, replayed from a
+ * captured HIP graph
  * (captured once per (buffers, nsteps) and cached in the plan).  J is exchanged once, at
  * the first step (summed in PSATD_J_DEPOSITED mode, filled from the owners in
  * PSATD_J_REPLICATED mode), and then held: the step never writes J, so the later steps
@@ -199,17 +206,22 @@ psatd_status psatd_run(psatd_plan_t plan, void* const E[3], void* const B[3], vo
 psatd_status psatd_heat_run(psatd_plan_t plan, void* u, double diffusivity, int32_t nsteps);
 
 /*
- * psatd_run_profiled -- nsteps >= 1 steps (psatd_step semantics, J exchanged every step)
- * launched directly with a HIP event pair around every kernel launch; waits for
- * completion and writes the mean milliseconds per step of each phase to
- * phase_ms[PSATD_NPHASES] (host array).
+ * psatd_run_profiled -- nsteps >= 1 steps with psatd_run semantics (J exchanged at the
+ * first step only: summed in PSATD_J_DEPOSITED mode, owner-copied in
+ * PSATD_J_REPLICATED mode, then held), launched directly with a HIP event pair around
+ * every kernel launch; waits for completion and writes the mean milliseconds per step
+ * of each phase to phase_ms[PSATD_NPHASES] (host array; the J exchange's time is
+ * averaged over the nsteps steps).
  */
 psatd_status psatd_run_profiled(psatd_plan_t plan, void* const E[3], void* const B[3],
                                 void* const J[3], int32_t nsteps, double* phase_ms);
 
 /*
- * psatd_scatter -- global[3] (interior grid) -> padded[3] field buffers, guards filled
- * from the owners (a consistent state).  psatd_gather -- padded interiors -> global[3].
+ * psatd_scatter -- Fig. 3 step 1: global[3] (interior grid) -> padded[3] field buffers,
+ * every padded cell (guards included) taking the value at its global index modulo the
+ * grid (a consistent state).  psatd_gather -- padded interiors -> global[3] (each cell
+ * from the subdomain that owns it).  Exact copies; the global buffers hold
+ * grid_n[0] * grid_n[1] * grid_n[2] elements of the plan's element type.
  */
 psatd_status psatd_scatter(psatd_plan_t plan, const void* const global[3], void* const padded[3]);
 psatd_status psatd_gather(psatd_plan_t plan, const void* const padded[3], void* const global[3]);
@@ -233,8 +245,10 @@ psatd_status psatd_get_tuning(psatd_plan_t plan, int32_t key, int32_t* value);
 /*
  * psatd_autotune -- picks the launch shapes (largest radix, x/y threads, z tile and threads,
  * XCD item order) by timing candidate settings with steps_per_trial >= 1 steps each on the
- * given buffers, phase by phase, and applies the fastest.  The trial steps advance E and B
- * (tune before loading the state that matters).  cache_path (may be NULL): a text file of
+ * given buffers, phase by phase, and applies the fastest.  When it times (no cache hit), J is
+ * first exchanged once as psatd_step does (summed in PSATD_J_DEPOSITED mode) and then left
+ * alone by every trial; the trial steps advance E and B (tune before loading the state
+ * that matters).  cache_path (may be NULL): a text file of
  * "key value..." lines; a hit applies the cached setting without timing, a miss appends the
  * new result.  The key holds the device name, the precision and the padded box shapes.
  * *best_ms (may be NULL) receives the tuned step time in milliseconds (0 on a cache hit).

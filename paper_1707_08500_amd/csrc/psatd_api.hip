@@ -503,11 +503,14 @@ psatd_status psatd_heat_run(psatd_plan_t p, void* u, double diffusivity, int32_t
   return PSATD_OK;
 }
 
-psatd_status psatd_run_profiled(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3],
-                                int32_t nsteps, double* phase_ms) {
-  psatd_status r = check_step_args(p, E, B, J);
-  if (r != PSATD_OK) return r;
-  if (nsteps < 1 || !phase_ms) return fail(p, PSATD_E_INVALID, "nsteps < 1 or null phase_ms");
+namespace {
+
+// nsteps eager steps with an event pair around every launch.  exchange_J: the
+// first step exchanges J (sum in deposited mode, owner copy in replicated
+// mode); the later steps find it consistent (psatd_run semantics).  Without
+// it no step touches J.
+psatd_status run_profiled(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3], int32_t nsteps,
+                          double* phase_ms, bool exchange_J) {
   const size_t npairs = 2 + 3 * p->h.batches.size();
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev(npairs);
   psatd_status out = PSATD_OK;
@@ -522,10 +525,12 @@ psatd_status psatd_run_profiled(psatd_plan_t p, void* const E[3], void* const B[
   }
   double acc[kNumPhases] = {0, 0, 0, 0, 0};
   for (int stp = 0; stp < nsteps && out == PSATD_OK; ++stp) {
-    out = enqueue_step(p, E, B, J, p->stream, true, &ev);
+    const bool first = exchange_J && stp == 0;
+    const size_t used = first ? npairs : npairs - 1;  // pairs recorded by this step
+    out = enqueue_step(p, E, B, J, p->stream, first, &ev);
     if (out != PSATD_OK) break;
-    if (hipEventSynchronize(ev[npairs - 1].second.second) != hipSuccess) { out = fail(p, PSATD_E_HIP, "hipEventSynchronize"); break; }
-    for (size_t i = 0; i < npairs; ++i) {
+    if (hipEventSynchronize(ev[used - 1].second.second) != hipSuccess) { out = fail(p, PSATD_E_HIP, "hipEventSynchronize"); break; }
+    for (size_t i = 0; i < used; ++i) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, ev[i].second.first, ev[i].second.second) != hipSuccess) {
         out = fail(p, PSATD_E_HIP, "hipEventElapsedTime");
@@ -541,6 +546,16 @@ psatd_status psatd_run_profiled(psatd_plan_t p, void* const E[3], void* const B[
   if (out != PSATD_OK) return out;
   for (int ph = 0; ph < kNumPhases; ++ph) phase_ms[ph] = acc[ph] / nsteps;
   return PSATD_OK;
+}
+
+}  // namespace
+
+psatd_status psatd_run_profiled(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3],
+                                int32_t nsteps, double* phase_ms) {
+  psatd_status r = check_step_args(p, E, B, J);
+  if (r != PSATD_OK) return r;
+  if (nsteps < 1 || !phase_ms) return fail(p, PSATD_E_INVALID, "nsteps < 1 or null phase_ms");
+  return run_profiled(p, E, B, J, nsteps, phase_ms, true);
 }
 
 psatd_status psatd_scatter(psatd_plan_t p, const void* const global[3], void* const padded[3]) {
@@ -677,11 +692,11 @@ psatd_status psatd_get_tuning(psatd_plan_t p, int32_t key, int32_t* value) {
 
 namespace {
 
-// Mean ms per step of each phase over nsteps (psatd_run_profiled without the
-// argument checks).
+// Mean ms per step of each phase over nsteps, J left as it is (the tuner has
+// exchanged it once already).
 psatd_status time_phases(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3], int nsteps,
                          double* ms) {
-  return psatd_run_profiled(p, E, B, J, nsteps, ms);
+  return run_profiled(p, E, B, J, nsteps, ms, false);
 }
 
 std::string tune_key(psatd_plan_t p) {
@@ -723,6 +738,12 @@ psatd_status psatd_autotune(psatd_plan_t p, void* const E[3], void* const B[3], 
       return PSATD_OK;
     }
   }
+  // J is exchanged once, as psatd_step would (summed in deposited mode); the
+  // trial steps then leave it alone, so deposited currents are summed exactly
+  // once however many candidates are timed.
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  if (p->h.jmode == PSATD_J_DEPOSITED) HIPCHK(p, launch_sum(p->dp, J, p->stream));
+  HIPCHK(p, launch_fill(p->dp, J, 3, p->stream));
   // Phases are separate kernels: the x/y shape and the z shape are tuned
   // independently for each largest radix (which both share).
   double best_total = 1e300;

@@ -120,9 +120,28 @@ def validate(grid_n, grid_d, lo, n, guard, order_p, dt, c=1.0, precision="f64",
     return out.value
 
 
-def _ptrs(tensors):
+def check_buffer(t, dtype, numel, device, what):
+    """Raises ValueError unless tensor t is a contiguous CUDA tensor of the
+    given dtype, element count (None: any) and device: the C-ABI takes bare
+    device pointers and cannot check any of these itself."""
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"{what}: not a CUDA tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{what}: on {t.device}, the plan runs on {device}")
+    if t.dtype != dtype:
+        raise ValueError(f"{what}: dtype {t.dtype}, the plan needs {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: not contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what}: {t.numel()} elements, the plan needs {numel}")
+
+
+def _ptrs(tensors, dtype=None, numel=None, device=None, what="buffers"):
     if len(tensors) != 3:
-        raise ValueError("need 3 component buffers")
+        raise ValueError(f"{what}: need 3 component buffers")
+    if dtype is not None:
+        for i, t in enumerate(tensors):
+            check_buffer(t, dtype, numel, device, f"{what}[{i}]")
     return (ctypes.c_void_p * 3)(*[t.data_ptr() for t in tensors])
 
 
@@ -148,6 +167,8 @@ class Plan:
                             JMODES[jmode], ctypes.c_void_p(stream))
         _check(st)
         self._h = h
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.global_elems = self.grid_n[0] * self.grid_n[1] * self.grid_n[2]
         e = ctypes.c_int64(0)
         _check(LIB.psatd_field_elems(self._h, ctypes.byref(e)), self._h)
         self.field_elems = e.value
@@ -168,8 +189,15 @@ class Plan:
         if tensor is None:
             _check(LIB.psatd_set_workspace(self._h, None, 0), self._h)
         else:
+            check_buffer(tensor, tensor.dtype, None, self.device, "workspace")
             _check(LIB.psatd_set_workspace(self._h, ctypes.c_void_p(tensor.data_ptr()),
                                            tensor.numel() * tensor.element_size()), self._h)
+
+    def _fields(self, tensors, what):
+        return _ptrs(tensors, self.dtype, self.field_elems, self.device, what)
+
+    def _globals(self, tensors, what):
+        return _ptrs(tensors, self.dtype, self.global_elems, self.device, what)
 
     def empty_fields(self, device="cuda"):
         import torch
@@ -177,27 +205,32 @@ class Plan:
 
     # -- the step
     def step(self, E, B, J):
-        _check(LIB.psatd_step(self._h, _ptrs(E), _ptrs(B), _ptrs(J)), self._h)
+        _check(LIB.psatd_step(self._h, self._fields(E, "E"), self._fields(B, "B"), self._fields(J, "J")),
+               self._h)
 
     def run(self, E, B, J, nsteps):
-        _check(LIB.psatd_run(self._h, _ptrs(E), _ptrs(B), _ptrs(J), int(nsteps)), self._h)
+        _check(LIB.psatd_run(self._h, self._fields(E, "E"), self._fields(B, "B"), self._fields(J, "J"),
+                             int(nsteps)), self._h)
 
     def heat_run(self, u, diffusivity, nsteps):
         """psatd_heat_run: nsteps heat-equation steps of one padded field buffer."""
+        check_buffer(u, self.dtype, self.field_elems, self.device, "u")
         _check(LIB.psatd_heat_run(self._h, ctypes.c_void_p(u.data_ptr()), float(diffusivity),
                                   int(nsteps)), self._h)
 
     def run_profiled(self, E, B, J, nsteps):
         out = (ctypes.c_double * NPHASES)()
-        _check(LIB.psatd_run_profiled(self._h, _ptrs(E), _ptrs(B), _ptrs(J), int(nsteps), out),
-               self._h)
+        _check(LIB.psatd_run_profiled(self._h, self._fields(E, "E"), self._fields(B, "B"),
+                                      self._fields(J, "J"), int(nsteps), out), self._h)
         return dict(zip(PHASES, list(out)))
 
     def scatter(self, glob, padded):
-        _check(LIB.psatd_scatter(self._h, _ptrs(glob), _ptrs(padded)), self._h)
+        _check(LIB.psatd_scatter(self._h, self._globals(glob, "global"), self._fields(padded, "padded")),
+               self._h)
 
     def gather(self, padded, glob):
-        _check(LIB.psatd_gather(self._h, _ptrs(padded), _ptrs(glob)), self._h)
+        _check(LIB.psatd_gather(self._h, self._fields(padded, "padded"), self._globals(glob, "global")),
+               self._h)
 
     def modified_k(self, s, axis):
         pn, _ = self.layout(s)
@@ -224,8 +257,8 @@ class Plan:
         returns the tuned step time in ms (0.0 on a cache hit)."""
         out = ctypes.c_double(0.0)
         cp = cache_path.encode() if cache_path else None
-        _check(LIB.psatd_autotune(self._h, _ptrs(E), _ptrs(B), _ptrs(J), int(steps_per_trial), cp,
-                                  ctypes.byref(out)), self._h)
+        _check(LIB.psatd_autotune(self._h, self._fields(E, "E"), self._fields(B, "B"), self._fields(J, "J"),
+                                  int(steps_per_trial), cp, ctypes.byref(out)), self._h)
         return out.value
 
     def set_stream(self, stream):

@@ -33,6 +33,36 @@ def random_fields(N, seed, d=(1.0, 1.0, 1.0), p=8, divfree=True):
     return E, B, J
 
 
+def deposited_partition(J, dec, seed):
+    """Partial currents per padded copy: every global value of J split among
+    all its copies with random positive weights (deposited mode: the sum over
+    the copies is J)."""
+    N = dec.N
+    r = synth.rng(seed, synth.STREAM_PART)
+    Jrep = O.scatter(J, dec)
+    wts = [r.exponential(size=Jb.shape[1:]) for Jb in Jrep]
+    wsum = np.zeros((N[2], N[1], N[0]))
+    for s in range(dec.nsub):
+        ix, iy, iz = dec.global_index(s)
+        Z, Y, X = np.meshgrid(iz, iy, ix, indexing="ij")
+        np.add.at(wsum, (Z, Y, X), wts[s])
+    out = []
+    for s in range(dec.nsub):
+        ix, iy, iz = dec.global_index(s)
+        Z, Y, X = np.meshgrid(iz, iy, ix, indexing="ij")
+        out.append(J[:, Z, Y, X] * wts[s] / wsum[Z, Y, X])
+    return out
+
+
+def upload_boxes(case, bufs, boxes):
+    """Writes per-box padded arrays (3, Pz, Py, Px) into a plan's field buffers."""
+    import torch
+    for a in range(3):
+        host = np.concatenate([boxes[s][a].ravel() for s in range(case.dec.nsub)])
+        bufs[a].copy_(torch.from_numpy(host).to("cuda", case.dtype))
+    torch.cuda.synchronize()
+
+
 def config2_fields(N, d, p, case=2, sigma=8.0):
     """Gaussian current pulse, Gauss-law E from a mean-free Gaussian charge
     blob (with the same order-p [k]), B = 0."""

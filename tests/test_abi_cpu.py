@@ -119,3 +119,48 @@ def test_null_and_bad_plan_calls_are_errors_not_crashes():
     gd = (ctypes.c_double * 3)(1, 1, 1)
     st = L.psatd_plan(ctypes.byref(out), gn, gd, 0, None, None, None, 0, 0.5, 1.0, 0, 0, None)
     assert st == 1 and not out.value
+
+
+class _FakeCuda:
+    """Stands in for a CUDA tensor on a machine without a GPU: only the
+    attributes the binding's buffer check reads."""
+
+    def __init__(self, dtype, numel, device="cuda:0", contiguous=True):
+        import torch
+        self.is_cuda = True
+        self.dtype = dtype
+        self.device = torch.device(device)
+        self._n = numel
+        self._c = contiguous
+
+    def numel(self):
+        return self._n
+
+    def is_contiguous(self):
+        return self._c
+
+
+def test_binding_rejects_mismatched_buffers_before_the_abi():
+    """The C-ABI takes bare device pointers, so the binding checks every
+    tensor first: a host tensor, another device, the wrong dtype (FP32 data
+    for an FP64 plan), a strided view, or a buffer of the wrong length (e.g.
+    global and padded buffers swapped) is a ValueError, never a launch."""
+    import torch
+    from paper_1707_08500_amd import psatd
+    dev = torch.device("cuda:0")
+    ok = _FakeCuda(torch.float64, 1000)
+    psatd.check_buffer(ok, torch.float64, 1000, dev, "E[0]")
+    cases = [
+        (torch.zeros(1000, dtype=torch.float64), "not a CUDA tensor"),
+        (_FakeCuda(torch.float64, 1000, device="cuda:1"), "the plan runs on"),
+        (_FakeCuda(torch.float32, 1000), "the plan needs torch.float64"),
+        (_FakeCuda(torch.float64, 1000, contiguous=False), "not contiguous"),
+        (_FakeCuda(torch.float64, 512), "elements, the plan needs 1000"),
+    ]
+    for t, msg in cases:
+        with pytest.raises(ValueError, match=msg):
+            psatd.check_buffer(t, torch.float64, 1000, dev, "E[0]")
+    with pytest.raises(ValueError, match="need 3 component buffers"):
+        psatd._ptrs([ok, ok], torch.float64, 1000, dev, "E")
+    with pytest.raises(ValueError, match=r"B\[2\]"):
+        psatd._ptrs([ok, ok, _FakeCuda(torch.float64, 999)], torch.float64, 1000, dev, "B")

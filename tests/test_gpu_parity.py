@@ -13,7 +13,8 @@ import pytest
 from oracle import psatd_oracle as O
 from paper_1707_08500_amd import synth
 
-from psatd_cases import GpuCase, boxes_rel_l2, config2_fields, energy_rel_l2, random_fields, say
+from psatd_cases import (GpuCase, boxes_rel_l2, config2_fields, deposited_partition, energy_rel_l2,
+                         random_fields, say, upload_boxes)
 
 pytestmark = pytest.mark.gpu
 
@@ -137,19 +138,7 @@ def test_step_uneven_deposited(precision, tol):
     N, lo, n, g = uneven_small()
     dec = O.Decomposition(N, lo, n, g)
     E, B, J = random_fields(N, 4, p=4)
-    Jrep = O.scatter(J, dec)
-    r = synth.rng(5, synth.STREAM_PART)
-    wts = [r.exponential(size=Jb.shape[1:]) for Jb in Jrep]
-    wsum = np.zeros((N[2], N[1], N[0]))
-    for s in range(dec.nsub):
-        ix, iy, iz = dec.global_index(s)
-        Z, Y, X = np.meshgrid(iz, iy, ix, indexing="ij")
-        np.add.at(wsum, (Z, Y, X), wts[s])
-    Jdep = []
-    for s in range(dec.nsub):
-        ix, iy, iz = dec.global_index(s)
-        Z, Y, X = np.meshgrid(iz, iy, ix, indexing="ij")
-        Jdep.append(J[:, Z, Y, X] * wts[s] / wsum[Z, Y, X])
+    Jdep = deposited_partition(J, dec, 5)
     if precision == "f32":
         Jdep = [j.astype(np.float32).astype(np.float64) for j in Jdep]
         E, B = (x.astype(np.float32).astype(np.float64) for x in (E, B))
@@ -630,3 +619,36 @@ def test_caller_workspace_side_stream_and_profiled_run_are_the_same_step():
     for other in outs[1:]:
         for a, b in zip(outs[0], other):
             assert torch.equal(a, b)
+
+
+def test_autotune_and_profiled_run_sum_deposited_currents_once(tmp_path):
+    """Deposited currents are summed exactly once per deposit: by the
+    autotuner however many trials it times, and by a multi-step profiled run,
+    so the state after either matches the decomposed oracle."""
+    say("deposited J: autotune and profiled run sum once")
+    N, lo, n, g = uneven_small()
+    dec = O.Decomposition(N, lo, n, g)
+    E, B, J = random_fields(N, 31, p=4)
+    Jdep = deposited_partition(J, dec, 32)
+    case = GpuCase(N, lo, n, g, 4, 0.3, 1.0, "f64", "deposited", E, B, J)
+    upload_boxes(case, case.J, Jdep)
+    case.plan.autotune(case.E, case.B, case.J, steps_per_trial=2, cache_path=str(tmp_path / "t.txt"))
+    case.plan.sync()
+    oJ = O.exchange_sum(Jdep, dec)
+    gJ = case.boxes(case.J)
+    assert max(boxes_rel_l2(gJ, oJ)) <= 1e-14
+    # fresh partial currents and the initial E, B: 3 profiled steps, then 2 graph steps
+    import torch
+    for glob, pad in ((E, case.E), (B, case.B)):
+        case.plan.scatter([torch.from_numpy(np.ascontiguousarray(glob[a])).to("cuda", case.dtype).reshape(-1)
+                           for a in range(3)], pad)
+    upload_boxes(case, case.J, Jdep)
+    case.plan.run_profiled(case.E, case.B, case.J, 3)
+    case.plan.sync()
+    oE, oB, oJ3 = O.run_local(O.scatter(E, dec), O.scatter(B, dec), Jdep, dec, (1.0, 1.0, 1.0), 4, 1.0, 0.3, 3,
+                              "deposited")
+    gE, gB = case.boxes(case.E), case.boxes(case.B)
+    eE, eB = boxes_rel_l2(gE, oE), boxes_rel_l2(gB, oB)
+    say(f"  after autotune + 3 profiled steps: rel-L2 E {eE} B {eB}")
+    assert max(eE + eB) <= TOL64
+    assert max(boxes_rel_l2(case.boxes(case.J), oJ3)) <= 1e-14
