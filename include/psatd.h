@@ -179,6 +179,23 @@ psatd_status psatd_set_workspace(psatd_plan_t plan, void* dev, int64_t bytes);
 psatd_status psatd_step(psatd_plan_t plan, void* const E[3], void* const B[3], void* const J[3]);
 
 /*
+ * psatd_step_noalloc -- psatd_step for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same step and results, with the spectral workspace taken from a static device array of
+ * PSATD_NOALLOC_SCRATCH_BYTES bytes that the library holds on every GPU it runs on until
+ * the process ends, instead of the plan's or the caller's workspace.  It calls no
+ * allocating routine.  Returns PSATD_E_INVALID (nothing enqueued) when
+ * psatd_workspace_bytes exceeds that size: batching the boxes (PSATD_TUNE_BATCH_BOXES)
+ * shrinks the workspace to one batch.  Every call on a GPU shares that GPU's array
+ * (nothing in it needs to start at zero; it keeps the last call's contents), so calls
+ * that overlap in time on one GPU, from any plans or streams, race and must be ordered
+ * by the caller.
+ */
+#define PSATD_NOALLOC_SCRATCH_BYTES (64ll << 20)
+psatd_status psatd_step_noalloc(psatd_plan_t plan, void* const E[3], void* const B[3],
+                                void* const J[3]);
+
+/*
  * psatd_run -- nsteps >= 0 steps of Sec. 3.2 / Fig. 3 with J unchanged, replayed from a
  * captured HIP graph
  * (captured once per (buffers, nsteps) and cached in the plan).  J is exchanged once, at

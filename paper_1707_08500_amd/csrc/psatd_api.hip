@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <cstring>
 #include <new>
@@ -23,6 +24,34 @@ using namespace psatd;
 namespace {
 
 thread_local std::string g_last_error = "";
+
+// Spectral workspace of psatd_step_noalloc: a file-scope device array, one
+// copy per GPU, alive until the process ends.  In host code `scratch` only
+// names the symbol; its device address on each GPU comes from
+// hipGetSymbolAddress, resolved once per device at plan creation with that
+// device current, and only that address is ever passed to a kernel.
+constexpr int64_t kScratchBytes = PSATD_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) static unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void* scratch_of(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 struct GraphEntry {
   void* ptr[9];
@@ -129,8 +158,10 @@ psatd_status check_fields(psatd_plan_t p, void* const* v, int count, const char*
 // later steps of a run with J held fixed find it already consistent.
 psatd_status enqueue_step(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3],
                           hipStream_t st, bool first,
-                          std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>* prof = nullptr) {
+                          std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>* prof = nullptr,
+                          void* ws = nullptr) {
   const DevPlan& d = p->dp;
+  if (!ws) ws = p->ws;
   void* eb[6] = {E[0], E[1], E[2], B[0], B[1], B[2]};
   void* in9[9] = {E[0], E[1], E[2], B[0], B[1], B[2], J[0], J[1], J[2]};
   size_t ip = 0;
@@ -158,21 +189,21 @@ psatd_status enqueue_step(psatd_plan_t p, void* const E[3], void* const B[3], vo
   for (const Batch& b : p->h.batches) {
     PSATD_MARK(kPhaseFwd, true);
     if (d.split) {
-      HIPCHK(p, launch_x_fwd(d, in9, p->ws, st));
-      HIPCHK(p, launch_y(d, -1, p->ws, st));
+      HIPCHK(p, launch_x_fwd(d, in9, ws, st));
+      HIPCHK(p, launch_y(d, -1, ws, st));
     } else {
-      HIPCHK(p, launch_fwd(d, b, in9, p->ws, st));
+      HIPCHK(p, launch_fwd(d, b, in9, ws, st));
     }
     PSATD_MARK(kPhaseFwd, false);
     PSATD_MARK(kPhaseUpd, true);
-    HIPCHK(p, launch_upd(d, b, p->ws, st));
+    HIPCHK(p, launch_upd(d, b, ws, st));
     PSATD_MARK(kPhaseUpd, false);
     PSATD_MARK(kPhaseInv, true);
     if (d.split) {
-      HIPCHK(p, launch_y(d, 1, p->ws, st));
-      HIPCHK(p, launch_x_inv(d, p->ws, eb, st));
+      HIPCHK(p, launch_y(d, 1, ws, st));
+      HIPCHK(p, launch_x_inv(d, ws, eb, st));
     } else {
-      HIPCHK(p, launch_inv(d, b, p->ws, eb, st));
+      HIPCHK(p, launch_inv(d, b, ws, eb, st));
     }
     PSATD_MARK(kPhaseInv, false);
   }
@@ -254,6 +285,7 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   };
   hipError_t e;
   if ((e = hipGetDevice(&p->device)) != hipSuccess) return hipfail(e, "hipGetDevice");
+  if ((e = resolve_scratch(p->device)) != hipSuccess) return hipfail(e, "hipGetSymbolAddress(scratch)");
   if ((e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess)
     return hipfail(e, "hipStreamCreateWithFlags");
 
@@ -438,6 +470,22 @@ psatd_status psatd_step(psatd_plan_t p, void* const E[3], void* const B[3], void
   psatd_status r = check_step_args(p, E, B, J);
   if (r != PSATD_OK) return r;
   return enqueue_step(p, E, B, J, p->stream, true);
+}
+
+psatd_status psatd_step_noalloc(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3]) {
+  if (!p) return fail(nullptr, PSATD_E_INVALID, "null plan");
+  psatd_status r;
+  if ((r = check_fields(p, E, 3, "E")) != PSATD_OK) return r;
+  if ((r = check_fields(p, B, 3, "B")) != PSATD_OK) return r;
+  if ((r = check_fields(p, J, 3, "J")) != PSATD_OK) return r;
+  const int64_t need = workspace_need(p);
+  if (need > kScratchBytes)
+    return fail(p, PSATD_E_INVALID,
+                "the plan's workspace (" + std::to_string(need) + " bytes) exceeds the static scratch of " +
+                    std::to_string(kScratchBytes) + " bytes; batch the boxes (PSATD_TUNE_BATCH_BOXES)");
+  void* ws = scratch_of(p->device);
+  if (!ws) return fail(p, PSATD_E_STATE, "static scratch not resolved on the plan's device");
+  return enqueue_step(p, E, B, J, p->stream, true, nullptr, ws);
 }
 
 psatd_status psatd_run(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3],

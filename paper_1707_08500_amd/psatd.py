@@ -27,12 +27,13 @@ TUNING = {"z_pencils": 0, "xcd_remap": 1, "grid_fwd": 2, "grid_upd": 3, "grid_in
           "grid_exch": 5, "batch_boxes": 6, "max_radix": 7, "xy_threads": 8, "z_threads": 9,
           "split_xy": 10, "fuse_eb": 11}
 NPHASES = len(PHASES)
+NOALLOC_SCRATCH_BYTES = 64 << 20  # PSATD_NOALLOC_SCRATCH_BYTES
 
 STATUS = {0: "PSATD_OK", 1: "PSATD_E_INVALID", 2: "PSATD_E_NOMEM", 3: "PSATD_E_HIP",
           4: "PSATD_E_UNSUPPORTED", 5: "PSATD_E_STATE"}
 
 SYMBOLS = ("psatd_plan", "psatd_validate", "psatd_field_elems", "psatd_field_layout",
-           "psatd_workspace_bytes", "psatd_set_workspace", "psatd_step", "psatd_run", "psatd_heat_run",
+           "psatd_workspace_bytes", "psatd_set_workspace", "psatd_step", "psatd_step_noalloc", "psatd_run", "psatd_heat_run",
            "psatd_run_profiled", "psatd_scatter", "psatd_gather", "psatd_modified_k",
            "psatd_set_tuning", "psatd_get_tuning", "psatd_autotune", "psatd_set_stream", "psatd_sync", "psatd_destroy", "psatd_status_string",
            "psatd_last_error", "psatd_version")
@@ -62,6 +63,7 @@ def _load():
         "psatd_workspace_bytes": ([P, I64P], i32),
         "psatd_set_workspace": ([P, P, i64], i32),
         "psatd_step": ([P, VPP, VPP, VPP], i32),
+        "psatd_step_noalloc": ([P, VPP, VPP, VPP], i32),
         "psatd_run": ([P, VPP, VPP, VPP, i32], i32),
         "psatd_run_profiled": ([P, VPP, VPP, VPP, i32, DP], i32),
         "psatd_heat_run": ([P, P, f64, i32], i32),
@@ -207,6 +209,12 @@ class Plan:
     def step(self, E, B, J):
         _check(LIB.psatd_step(self._h, self._fields(E, "E"), self._fields(B, "B"), self._fields(J, "J")),
                self._h)
+
+    def step_noalloc(self, E, B, J):
+        """psatd_step_noalloc: one step with the library's static device scratch as the
+        workspace (no allocation anywhere in the call)."""
+        _check(LIB.psatd_step_noalloc(self._h, self._fields(E, "E"), self._fields(B, "B"),
+                                      self._fields(J, "J")), self._h)
 
     def run(self, E, B, J, nsteps):
         _check(LIB.psatd_run(self._h, self._fields(E, "E"), self._fields(B, "B"), self._fields(J, "J"),
