@@ -109,16 +109,23 @@ def random_unit_vectors(r, count):
     return v / np.linalg.norm(v, axis=1, keepdims=True)
 
 
+def current_pulse_params(grid_n, d, case, count=1, amp_range=(0.5, 1.0)):
+    """The draws behind current_pulses: centres (count, 3) uniform on the grid,
+    amplitudes uniform in amp_range, directions uniform on the sphere."""
+    r = rng(case, STREAM_J)
+    L = np.array([grid_n[u] * d[u] for u in range(3)])
+    centres = r.uniform(0.0, 1.0, size=(count, 3)) * L
+    amps = r.uniform(amp_range[0], amp_range[1], size=count)
+    dirs = random_unit_vectors(r, count)
+    return centres, amps, dirs
+
+
 def current_pulses(grid_n, d, case, count=1, sigma=8.0, amp_range=(0.5, 1.0)):
     """Sum of `count` Gaussian current pulses: centre uniform on the grid,
     amplitude uniform in amp_range, direction uniform on the sphere.
     Returns (3, Nz, Ny, Nx) float64."""
-    r = rng(case, STREAM_J)
-    L = np.array([grid_n[u] * d[u] for u in range(3)])
+    centres, amps, dirs = current_pulse_params(grid_n, d, case, count, amp_range)
     J = np.zeros((3, grid_n[2], grid_n[1], grid_n[0]))
-    centres = r.uniform(0.0, 1.0, size=(count, 3)) * L
-    amps = r.uniform(amp_range[0], amp_range[1], size=count)
-    dirs = random_unit_vectors(r, count)
     for i in range(count):
         g = gaussian_blob(grid_n, d, centres[i], sigma) * amps[i]
         for a in range(3):

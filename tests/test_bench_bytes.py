@@ -60,3 +60,24 @@ def test_fp64_writes_without_reading_and_fused_exchange_moves_nothing():
     fused, _ = bench.algorithmic_bytes(FakePlan(padded, "f64", fuse=1), lo, n, g, 8)
     assert fused["exchange_EB"] == 0
     assert fused["fft_xy_inv"] == out["fft_xy_inv"] + boxes * (P ** 3 - I ** 3) * 6 * 8
+
+
+def test_roofline_block_is_bmin_over_the_dominant_kernel():
+    """roofline.achieved follows the survey's measurement rule: B_min = 15
+    reals (read E, B, J; write E, B) per padded cell per step, over the
+    event-timed launch of the dominant kernel; the kernel's own algorithmic
+    bytes over the same time are reported beside it."""
+    lo, n, g, padded = cfg2()
+    algo, _ = bench.algorithmic_bytes(FakePlan(padded, "f32"), lo, n, g, 4)
+    res = {"phases_ms": {"exchange_J": 0.05, "fft_xy_fwd": 1.0, "z_update": 1.25, "fft_xy_inv": 0.5,
+                         "exchange_EB": 0.5},
+           "algo_bytes": algo, "ms_per_step": 3.3,
+           "tuning": {"split_xy": 0, "z_pencils": 8, "z_threads": 512, "max_radix": 16, "xy_threads": 256}}
+    rf = bench.roofline_block("no_such_workload", res, "f32", (lo, n, g))
+    cells = 64 * 96 ** 3
+    assert rf["kernel"] == "z_update" and rf["bytes_per_launch"] == 15 * 4 * cells
+    assert abs(rf["achieved"] - 15 * 4 * cells / 1.25e-3 / 1e9) < 1e-6
+    assert abs(rf["frac"] - rf["achieved"] / 8000.0) < 1e-12
+    assert abs(rf["kernel_own"]["achieved"] - algo["z_update"] / 1.25e-3 / 1e9) < 1e-6
+    assert rf["traffic"] is None
+    assert rf["kernel_instance"] == "psatd::k_z_update<float, 512, 8, true, 16, 0>"
