@@ -44,6 +44,7 @@ PHASE_KERNEL = {"fft_xy_fwd": "k_fwd_xy", "z_update": "k_z_update", "fft_xy_inv"
                 "exchange_EB": "k_fill", "exchange_J": "k_fill"}
 COPY_BYTES = 1 << 30  # the calibration copy: 2^28 floats read and written
 NAMES = ("Ex", "Ey", "Ez", "Bx", "By", "Bz")
+TUNE = []  # launch-shape knobs from --tune, applied to every plan
 
 WORKLOADS = {
     "cfg2": dict(N=(256, 256, 256), nbox=(4, 4, 4), guard=16, p=32, dt=0.5, recipe="pulse_waves", case=2,
@@ -282,13 +283,13 @@ def summarize_ktrace(stats_csv, bench_line, workload, command):
     return "\n".join(lines) + "\n"
 
 
-def summarize_mix(a_csv, b_csv, workload, command):
-    """VALU instruction mix per dispatch of every psatd kernel from two
-    rocprofv3 --pmc passes: SQ_INSTS_VALU, the F64 kinds, SQ_INSTS_LDS,
-    SQ_INSTS_SALU and SQ_INSTS_VALU_INT32 in the first, the F32 kinds and
-    SQ_INSTS_VALU_CVT in the second (wave instructions, mean over dispatches)."""
+def summarize_mix(csvs, workload, command):
+    """VALU instruction mix per dispatch of every psatd kernel from rocprofv3
+    --pmc passes (SQ_INSTS_VALU with its INT32, F32, F64 and CVT kinds,
+    SQ_INSTS_LDS, SQ_INSTS_SALU; wave instructions, mean over dispatches), and
+    every other counter of the passes as its mean per dispatch."""
     per = {}
-    for path in (a_csv, b_csv):
+    for path in csvs:
         for r in csv.DictReader(open(path)):
             if "psatd" not in r["Kernel_Name"]:
                 continue
@@ -404,6 +405,11 @@ def measure_form(wl_name, wl, dec, inputs, prec, steps, warmup, profile_steps, g
     N, d = wl["N"], (1.0, 1.0, 1.0)
     torch.cuda.empty_cache()
     plan = psatd.Plan(N, d, lo, n, g, wl["p"], wl["dt"], 1.0, precision=prec)
+    for kv in TUNE:
+        try:
+            plan.set_tuning(**kv)
+        except psatd.PsatdError as err:
+            log(f"[bench] {wl_name} {prec}: tuning {kv} not applied ({err})")
     E, B, J = plan.empty_fields(), plan.empty_fields(), plan.empty_fields()
     if autotune:
         load_state(plan, inputs, E, B, J)
@@ -560,6 +566,8 @@ def main():
     ap.add_argument("--precisions", default="f32,bf16x3,bf16x6",
                     help="FP32-state forms to time (comma list of f32, bf16x3, bf16x6)")
     ap.add_argument("--profile-steps", type=int, default=5)
+    ap.add_argument("--tune", default="",
+                    help="launch-shape knobs applied to every plan, e.g. z_reg=0,z_pencils=4 (A/B runs)")
     ap.add_argument("--autotune", action="store_true",
                     help="time launch-shape candidates first (the defaults are the measured best)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -567,11 +575,14 @@ def main():
     ap.add_argument("--pmc-command", default="", help="the profiled command, recorded in the summary")
     ap.add_argument("--summarize-ktrace", nargs=2, metavar=("KERNEL_STATS_CSV", "BENCH_LOG"),
                     help="print the kernel-statistics summary of a rocprofv3 --stats run and exit")
-    ap.add_argument("--summarize-mix", nargs=2, metavar=("PASS_A_CSV", "PASS_B_CSV"),
-                    help="print the VALU instruction-mix summary of two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--summarize-mix", nargs="+", metavar="PASS_CSV",
+                    help="print the instruction-mix and counter summary of rocprofv3 --pmc runs and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
+    for item in filter(None, args.tune.split(",")):
+        k, v = item.split("=")
+        TUNE.append({k.strip(): int(v)})
     if args.summarize_pmc:
         text = summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload,
                              args.pmc_command)
@@ -588,8 +599,7 @@ def main():
               end="")
         return
     if args.summarize_mix:
-        print(summarize_mix(args.summarize_mix[0], args.summarize_mix[1], args.workload, args.pmc_command),
-              end="")
+        print(summarize_mix(args.summarize_mix, args.workload, args.pmc_command), end="")
         return
     if args.gpus != 1:
         print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "

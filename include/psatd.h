@@ -110,7 +110,10 @@ typedef enum {
                                  of its cell, so the E,B exchange needs no pass of its own (same bytes
                                  as the copy pass); 0 (default, faster on 96^3 boxes): a separate copy
                                  pass.  Batching (PSATD_TUNE_BATCH_BOXES) turns it off. */
-  PSATD_NTUNE = 12
+  PSATD_TUNE_Z_REG = 12,      /* 1: the FP32 VALU z pass holds each z transform in registers (compiled
+                                 padded z lengths only, unbatched plans); 0 (default, faster on 96^3 and
+                                 176^3 boxes): the LDS-staged z pass */
+  PSATD_NTUNE = 13
 } psatd_tune_key;
 
 /*

@@ -53,6 +53,9 @@ struct HostTables {
   int spl = 0;        // BF16 terms of the matrix-core first stage (0: VALU form)
   int ntxy = 512;     // threads per work-group of the x/y passes
   int ntu = 512;      // threads per work-group of the z-update (1024 for FP32 by default)
+  bool zreg = false;  // the register z pass applies (FP32 VALU form, every padded z length scheduled)
+  std::vector<ZGroup> zgroups;    // one per distinct padded z length
+  std::vector<int32_t> itemsZR;   // their work lists, nsub + 1 prefix entries each
 };
 
 inline bool is_f64(int prec) { return prec == PSATD_F64; }
@@ -358,6 +361,45 @@ inline void build_push(HostTables& h) {
     for (int32_t i = h.itemsG[b]; i < h.itemsG[b + 1]; ++i) h.pieceOf[i] = (int32_t)b;
 }
 
+// Pencils per work-group of the register z pass for padded z length N (0: no schedule).
+inline int zreg_pencils_of(int N) {
+#define PSATD_ZREG_P(N_, L_, W_, MINW_) \
+  if (N == N_) return zreg_pencils(L_, W_);
+  PSATD_ZREG_SHAPES(PSATD_ZREG_P)
+#undef PSATD_ZREG_P
+  return 0;
+}
+
+// Groups of the register z pass: every distinct padded z length must have a
+// schedule (else the LDS-staged z pass runs for all boxes).
+inline void build_zreg(HostTables& h) {
+  h.zreg = false;
+  h.zgroups.clear();
+  h.itemsZR.clear();
+  if (h.prec != PSATD_F32_VALU) return;
+  std::vector<int> lens;
+  for (const BoxD& b : h.box)
+    if (std::find(lens.begin(), lens.end(), b.P[2]) == lens.end()) lens.push_back(b.P[2]);
+  if ((int)lens.size() > kMaxZGroups) return;
+  for (int N : lens)
+    if (!zreg_pencils_of(N)) return;
+  for (const BoxD& b : h.box)  // the kernel addresses a box's 9 fields with 32-bit byte offsets
+    if (9 * b.svol * 8 >= ((int64_t)1 << 31)) return;
+  for (int N : lens) {
+    const int P = zreg_pencils_of(N);
+    ZGroup g{N, (int32_t)h.itemsZR.size(), 0, 0};
+    int32_t acc = 0;
+    h.itemsZR.push_back(0);
+    for (const BoxD& b : h.box) {
+      if (b.P[2] == N) acc += (int32_t)(((int64_t)b.P[1] * b.H + P - 1) / P);
+      h.itemsZR.push_back(acc);
+    }
+    g.n = acc;
+    h.zgroups.push_back(g);
+  }
+  h.zreg = true;
+}
+
 // Does the circular interval [a, a+len) (len < N) meet [lo, lo+n) on Z_N?
 inline bool circ_meets(int64_t a, int64_t len, int64_t lo, int64_t n, int64_t N) {
   if (len >= N) return true;
@@ -475,6 +517,7 @@ inline psatd_status build_host(HostTables& h, std::string& err, const int64_t gr
     b.kz = add_kentry(h, b.P[2], grid_d[2]);
     b.foff = foff;
     b.soff = soff;
+    b.svol = (int64_t)b.H * b.P[1] * b.P[2];
     foff += (int64_t)b.P[0] * b.P[1] * b.P[2];
     soff += (int64_t)b.H * b.P[1] * b.P[2];
     // plane + twiddles of the x plan, the y plan and W_Px + position tables
@@ -539,6 +582,7 @@ inline psatd_status build_host(HostTables& h, std::string& err, const int64_t gr
   prefix(h.itemsYI, [](const BoxD& b) { return (int64_t)b.n[2] * 6 * ((b.H + kCB - 1) / kCB); });
   prefix(h.itemsXI, [](const BoxD& b) { return (int64_t)b.n[2] * 6 * ((b.n[1] + kRB - 1) / kRB); });
   build_push(h);
+  build_zreg(h);
   set_batches(h, 0);
   // launch-shape defaults (measured on 96^3 and 176^3 boxes): x/y groups of
   // the fewest threads that still keep 16 waves on a CU given how many planes

@@ -71,7 +71,7 @@ struct psatd_plan_s {
   int device = 0;
   void* blob = nullptr;  // device tables
   int32_t* d_itemsU = nullptr;  // z-update work list (depends on the z tile)
-  int32_t tune[PSATD_NTUNE] = {0, 1, 0, 0, 0, 0, 0, 16, 256, 512, 0, 1};
+  int32_t tune[PSATD_NTUNE] = {0, 1, 0, 0, 0, 0, 0, 16, 256, 512, 0, 1, 0};
   void* ws = nullptr;
   int64_t ws_bytes = 0;
   bool ws_owned = false;
@@ -196,7 +196,10 @@ psatd_status enqueue_step(psatd_plan_t p, void* const E[3], void* const B[3], vo
     }
     PSATD_MARK(kPhaseFwd, false);
     PSATD_MARK(kPhaseUpd, true);
-    HIPCHK(p, launch_upd(d, b, ws, st));
+    if (d.zreg && p->h.batches.size() == 1)
+      HIPCHK(p, launch_upd_reg(d, ws, st));
+    else
+      HIPCHK(p, launch_upd(d, b, ws, st));
     PSATD_MARK(kPhaseUpd, false);
     PSATD_MARK(kPhaseInv, true);
     if (d.split) {
@@ -319,6 +322,7 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   const size_t o_iG = reserve(h.itemsG.size() * 4);
   const size_t o_fp = reserve(std::max<size_t>(h.fillp.size(), 1) * sizeof(FillPiece));
   const size_t o_pOf = reserve(std::max<size_t>(h.pieceOf.size(), 1) * 4);
+  const size_t o_iZR = reserve(std::max<size_t>(h.itemsZR.size(), 1) * 4);
   std::vector<unsigned char> hb(total, 0);
   auto put = [&](size_t off, const void* src, size_t bytes) {
     if (bytes) std::memcpy(hb.data() + off, src, bytes);
@@ -345,6 +349,7 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   put(o_iG, h.itemsG.data(), h.itemsG.size() * 4);
   put(o_fp, h.fillp.data(), h.fillp.size() * sizeof(FillPiece));
   put(o_pOf, h.pieceOf.data(), h.pieceOf.size() * 4);
+  put(o_iZR, h.itemsZR.data(), h.itemsZR.size() * 4);
   if ((e = hipMalloc(&p->blob, total)) != hipSuccess) return hipfail(e, "hipMalloc(tables)");
   if ((e = hipMemcpy(p->blob, hb.data(), total, hipMemcpyHostToDevice)) != hipSuccess)
     return hipfail(e, "hipMemcpy(tables)");
@@ -399,6 +404,11 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   d.pieceOf = reinterpret_cast<const int32_t*>(B + o_pOf);
   d.npiece = (int32_t)h.push.size();
   d.nG = h.itemsG.back();
+  d.itemsZR = reinterpret_cast<const int32_t*>(B + o_iZR);
+  d.nzg = (int32_t)h.zgroups.size();
+  for (int i = 0; i < d.nzg; ++i) d.zg[i] = h.zgroups[i];
+  d.zreg = 0;  // opt-in: measured slower than the LDS-staged z pass on 96^3 and 176^3 boxes
+  p->tune[PSATD_TUNE_Z_REG] = d.zreg;
   d.fuse = (h.fuse_eb && h.batches.size() == 1) ? 1 : 0;
   d.spl = h.spl;
   p->tune[PSATD_TUNE_FUSE_EB] = d.fuse;
@@ -684,6 +694,12 @@ psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
       d.fuse = value;
       break;
     }
+    case PSATD_TUNE_Z_REG:
+      if (value != 0 && value != 1) return fail(p, PSATD_E_INVALID, "z_reg must be 0 or 1");
+      if (value && !p->h.zreg)
+        return fail(p, PSATD_E_INVALID, "no register z schedule for this plan (FP32 VALU form, compiled lengths)");
+      d.zreg = value;
+      break;
     case PSATD_TUNE_XCD_REMAP:
       if (value != 0 && value != 1) return fail(p, PSATD_E_INVALID, "xcd remap must be 0 or 1");
       d.xcd = value;
@@ -721,7 +737,7 @@ psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
       break;
     default: {
       if (value < 0) return fail(p, PSATD_E_INVALID, "grid size must be >= 0");
-      static const int phase_of[] = {0, 0, kPhaseFwd, kPhaseUpd, kPhaseInv, kPhaseExchEB, 0, 0, 0, 0, 0, 0};
+      static const int phase_of[] = {0, 0, kPhaseFwd, kPhaseUpd, kPhaseInv, kPhaseExchEB, 0, 0, 0, 0, 0, 0, 0};
       d.grid_cap[phase_of[key]] = value;
       if (key == PSATD_TUNE_GRID_EXCH) d.grid_cap[kPhaseExchJ] = value;
     }

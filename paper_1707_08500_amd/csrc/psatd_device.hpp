@@ -33,8 +33,22 @@ struct BoxD {
   int32_t kx, ky, kz;  // offsets of the FP64 modified-wavenumber tables
   int32_t pad_;
   int64_t foff;    // element offset of the box in a field buffer
-  int64_t soff;    // complex-element offset of the box in one spectral field slab
+  int64_t soff;    // sum of the half-spectrum sizes of the boxes before it
+  int64_t svol;    // half-spectrum size of one field of the box, P[2] P[1] H (complex)
 };
+
+// The spectral workspace is box-major: box s holds the half spectra of its 9
+// fields back to back, field f at 9 soff + f svol (complex elements, relative
+// to the first box of the batch the workspace holds), [z][ky][kx] each.  So
+// every field of a box lies within 9 svol elements of the box's first one.
+template <typename T>
+PSATD_HD cx<T>* spec_at(cx<T>* spec, const BoxD& bx, int64_t sbias, int f) {
+  return spec + 9 * (bx.soff - sbias) + f * bx.svol;
+}
+template <typename T>
+PSATD_HD const cx<T>* spec_at(const cx<T>* spec, const BoxD& bx, int64_t sbias, int f) {
+  return spec + 9 * (bx.soff - sbias) + f * bx.svol;
+}
 
 // A batch of boxes [b0, b1) for the FFT/update passes: its work-item ranges
 // and the spectral offset of box b0 (the workspace holds the batch only).
@@ -55,6 +69,22 @@ struct PushBlk {
   int32_t y0, ly, qy;
   int32_t x0, lx, qx;
 };
+
+// Register z pass: the padded z lengths with a register schedule, as
+// X(N, lanes per transform, waves per work-group, min waves per SIMD).
+#define PSATD_ZREG_SHAPES(X) \
+  X(96, 2, 4, 2)             \
+  X(176, 4, 4, 2)
+
+// A group of boxes sharing one padded z length: its work list is
+// itemsZR[off .. off + nsub] (a prefix over all boxes, zero for the others).
+struct ZGroup {
+  int32_t N, off, n, pad_;
+};
+constexpr int kMaxZGroups = 8;
+
+// Pencils per work-group of the register z pass (9 fields share its lanes).
+constexpr int zreg_pencils(int L, int W) { return (64 * W / L) / 9; }
 
 // Work list: item -> box by binary search in a prefix array (size nsub + 1).
 PSATD_HD int find_box(const int32_t* prefix, int nsub, int item) {
@@ -282,8 +312,7 @@ struct FwdArgs {
   const int32_t* items;    // prefix over boxes of P[2] * nfield
   int32_t nfield;
   const T* in[9];
-  cx<T>* spec;             // spectral slabs, field f at spec + f * slab
-  int64_t slab;
+  cx<T>* spec;             // spectral workspace (box-major, see spec_at)
   int64_t sbias;           // spectral offset of the first box held by spec
 };
 
@@ -338,7 +367,7 @@ PSATD_HD void body_fwd_xy(const FwdArgs<T>& a, int item, int tid, int nt, cx<T>*
   pair_pass_rows<true>(lds, Py, ld, Nh, twr, tid, nt);
   bar();
   eng.template dif<-1, MAXR>(lds, H, 1, ld, ply, twy, tid, nt, bar);
-  cx<T>* dst = a.spec + f * a.slab + (bx.soff - a.sbias) + (int64_t)z * Py * H;
+  cx<T>* dst = spec_at(a.spec, bx, a.sbias, f) + (int64_t)z * Py * H;
   copy_grid<8, cx<T>>(Py, H, tid, nt, [&](int, int ky, int kx) { return lds[posy[ky] * ld + kx]; },
                       [&](int i, int, int, cx<T> v) { dst[i] = v; });
 }
@@ -350,55 +379,119 @@ struct UpdConst {
   double c, dt;
 };
 
+// sin h and cos h in FP64: Cody-Waite reduction of h by multiples of pi/2
+// (the two-term pi/2 leaves r within about 1e-16 of its true value for any
+// |h| below 2^30), then the Taylor series of sin and cos on |r| <= pi/4 to
+// the r^19 and r^18 terms (truncation below 1e-19), then the quadrant.
+PSATD_HD void sincos_cw(double h, double* sh, double* ch) {
+  const double two_over_pi = 0.63661977236758134308;
+  const double pio2_hi = 1.5707963267948966;      // nearest double to pi/2
+  const double pio2_lo = 6.123233995736766036e-17;  // pi/2 - pio2_hi
+  const double n = rint(h * two_over_pi);
+  const double r = fma(-n, pio2_lo, fma(-n, pio2_hi, h));
+  const double r2 = r * r;
+  // sin r = r (1 - r^2/3! + r^4/5! - ...), cos r = 1 - r^2/2! + r^4/4! - ...
+  double ps = -1.0 / 121645100408832000.0;         // -1/19!
+  ps = fma(ps, r2, 1.0 / 355687428096000.0);       // 1/17!
+  ps = fma(ps, r2, -1.0 / 1307674368000.0);        // -1/15!
+  ps = fma(ps, r2, 1.0 / 6227020800.0);            // 1/13!
+  ps = fma(ps, r2, -1.0 / 39916800.0);             // -1/11!
+  ps = fma(ps, r2, 1.0 / 362880.0);                // 1/9!
+  ps = fma(ps, r2, -1.0 / 5040.0);                 // -1/7!
+  ps = fma(ps, r2, 1.0 / 120.0);                   // 1/5!
+  ps = fma(ps, r2, -1.0 / 6.0);                    // -1/3!
+  const double s = fma(ps * r2, r, r);
+  double pc = 1.0 / 6402373705728000.0;            // 1/18!
+  pc = fma(pc, r2, -1.0 / 20922789888000.0);       // -1/16!
+  pc = fma(pc, r2, 1.0 / 87178291200.0);           // 1/14!
+  pc = fma(pc, r2, -1.0 / 479001600.0);            // -1/12!
+  pc = fma(pc, r2, 1.0 / 3628800.0);               // 1/10!
+  pc = fma(pc, r2, -1.0 / 40320.0);                // -1/8!
+  pc = fma(pc, r2, 1.0 / 720.0);                   // 1/6!
+  pc = fma(pc, r2, -1.0 / 24.0);                   // -1/4!
+  pc = fma(pc, r2, 0.5);
+  const double c = fma(-pc, r2, 1.0);
+  const int q = (int)((int64_t)n & 3);
+  *sh = q == 0 ? s : (q == 1 ? c : (q == 2 ? -s : -c));
+  *ch = q == 0 ? c : (q == 1 ? -s : (q == 2 ? -c : s));
+}
+
+// The FP64 coefficients of Eqs. PSATD_1 / PSATD_2 at |[k]|^2 = k2 (Sec. 3.1):
+// th = c |[k]| dt, C - 1 = -2 sin^2(th/2) (no cancellation), S/(ck),
+// X1 = (1 - C)/|[k]|^2 = 2 sin^2(th/2)/|[k]|^2, X2 = (S/(ck) - dt)/|[k]|^2 (by
+// its series below th = 0.1, where the difference cancels); the k -> 0
+// limits at |[k]| = 0.  rc = 1/c.
+struct Coef64 {
+  double cm1, sck, x1, x2;
+};
+
+PSATD_HD Coef64 psatd_coef(double k2, double c, double rc, double dt) {
+  Coef64 r;
+  const double c2 = c * c;
+  if (k2 == 0.0) {
+    r.cm1 = 0.0;
+    r.sck = dt;
+    r.x1 = 0.5 * c2 * dt * dt;
+    r.x2 = -c2 * dt * dt * dt / 6.0;
+    return r;
+  }
+  const double rk = rsqrt(k2);
+  const double rk2 = rk * rk;
+  const double k = k2 * rk;
+  const double h = 0.5 * c * dt * k;  // th / 2
+  double sh, ch;
+  sincos_cw(h, &sh, &ch);
+  const double sh2 = sh * sh;
+  r.cm1 = -2.0 * sh2;
+  r.sck = (2.0 * sh * ch) * rk * rc;
+  r.x1 = 2.0 * sh2 * rk2;
+  const double t2 = 4.0 * h * h;
+  if (t2 < 1e-2) {
+    r.x2 = -c2 * dt * dt * dt *
+           (1.0 / 6.0 - t2 * (1.0 / 120.0 - t2 * (1.0 / 5040.0 - t2 * (1.0 / 362880.0 - t2 / 39916800.0))));
+  } else {
+    r.x2 = (r.sck - dt) * rk2;
+  }
+  return r;
+}
+
 // Eqs. PSATD_1 / PSATD_2 (general c) at one k-point; coefficients in FP64.
 //   E' = C E + i c^2 (S/ck) [k]xB - (S/ck) J + X1 [k]([k].E) + X2 [k]([k].J)
 //   B' = C B - i (S/ck) [k]xE + i (X1/c^2) [k]xJ
-// C = cos th, S = sin th, th = c|[k]|dt, X1 = (1-C)/|[k]|^2 = 2 sin^2(th/2)/|[k]|^2,
-// X2 = (S/ck - dt)/|[k]|^2 (series below th = 0.1); k -> 0 limits at |[k]| = 0.
+// with the coefficients of psatd_coef.
 //
 // INC: return the increments E' - E and B' - B instead (C replaced by
 // C - 1 = -2 sin^2(th/2), exact without cancellation).  The FP32 path moves the
 // increment through the FFTs: for resolved fields it is far smaller than E,
 // so the FFT roundoff, relative to what is transformed, shrinks with it.
-// JOINT_SINCOS: one sincos call (fewer instructions) or sin and cos as two
-// calls (fewer live registers: the matrix-core z tiles keep two tiles per CU).
-template <typename T, bool INC = false, bool JOINT_SINCOS = true>
-PSATD_HD void psatd_point(T* vr, T* vi /* E0 E1 E2 B0 B1 B2 J0 J1 J2 */, double kx, double ky,
-                          double kz, double c, double dt) {
-  const double k2 = kx * kx + ky * ky + kz * kz;
-  double C, Sck, X1, X2;
-  const double c2 = c * c;
-  const double rc = 1.0 / c;  // uniform: hoisted out of the k-point loop
-  if (k2 == 0.0) {
-    C = INC ? 0.0 : 1.0;
-    Sck = dt;
-    X1 = 0.5 * c2 * dt * dt;
-    X2 = -c2 * dt * dt * dt / 6.0;
-  } else {
-    // one division (1/k) per k-point; the rest are products
-    const double k = sqrt(k2);
-    const double rk = 1.0 / k, rk2 = rk * rk;
-    const double th = c * k * dt;
-    double sh, ch;
-    if (JOINT_SINCOS) {
-      sincos(0.5 * th, &sh, &ch);
-    } else {
-      sh = sin(0.5 * th);
-      ch = cos(0.5 * th);
-    }
-    C = INC ? -2.0 * sh * sh : 1.0 - 2.0 * sh * sh;
-    Sck = (2.0 * sh * ch) * rk * rc;
-    X1 = 2.0 * sh * sh * rk2;
-    const double t2 = th * th;
-    if (t2 < 1e-2) {
-      X2 = -c2 * dt * dt * dt *
-           (1.0 / 6.0 - t2 * (1.0 / 120.0 - t2 * (1.0 / 5040.0 - t2 * (1.0 / 362880.0 - t2 / 39916800.0))));
-    } else {
-      X2 = (Sck - dt) * rk2;
-    }
-  }
-  // The coefficients are FP64; the multiply-adds run in the state's type T
-  // (FP64 path: double; FP32 path: float, where they act on increments).
+// The coefficients of one k-point in the state's type T, evaluated in FP64
+// and rounded once: C (or C - 1 for increments), S/(ck), X1, X2, c^2 S/(ck),
+// X1/c^2, and the modified wave vector.
+template <typename T>
+struct UpdCoef {
+  T C, S, X1, X2, a1, x1c, kx, ky, kz;
+};
+
+template <typename T, bool INC>
+PSATD_HD UpdCoef<T> update_coef(double kx, double ky, double kz, double c, double rc, double dt) {
+  const Coef64 cf = psatd_coef(kx * kx + ky * ky + kz * kz, c, rc, dt);
+  UpdCoef<T> u;
+  u.C = (T)(INC ? cf.cm1 : 1.0 + cf.cm1);
+  u.S = (T)cf.sck;
+  u.X1 = (T)cf.x1;
+  u.X2 = (T)cf.x2;
+  u.a1 = (T)(c * c * cf.sck);
+  u.x1c = (T)(cf.x1 * (rc * rc));
+  u.kx = (T)kx;
+  u.ky = (T)ky;
+  u.kz = (T)kz;
+  return u;
+}
+
+// The update's multiply-adds in the state's type T (FP64 path: double; FP32
+// path: float, where they act on increments).
+template <typename T>
+PSATD_HD void update_apply(T* vr, T* vi /* E0 E1 E2 B0 B1 B2 J0 J1 J2 */, const UpdCoef<T>& u) {
   T er[3], ei[3], br[3], bi[3], jr[3], ji[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -406,11 +499,9 @@ PSATD_HD void psatd_point(T* vr, T* vi /* E0 E1 E2 B0 B1 B2 J0 J1 J2 */, double 
     br[a] = vr[3 + a]; bi[a] = vi[3 + a];
     jr[a] = vr[6 + a]; ji[a] = vi[6 + a];
   }
-  const T tkx = (T)kx, tky = (T)ky, tkz = (T)kz;
+  const T tkx = u.kx, tky = u.ky, tkz = u.kz;
   const T K[3] = {tkx, tky, tkz};
-  const T tC = (T)C, tS = (T)Sck, tX1 = (T)X1, tX2 = (T)X2;
-  const T a1 = (T)(c2 * Sck);
-  const T x1c = (T)(X1 * (rc * rc));
+  const T tC = u.C, tS = u.S, tX1 = u.X1, tX2 = u.X2, a1 = u.a1, x1c = u.x1c;
   const T kEr = tkx * er[0] + tky * er[1] + tkz * er[2];
   const T kEi = tkx * ei[0] + tky * ei[1] + tkz * ei[2];
   const T kJr = tkx * jr[0] + tky * jr[1] + tkz * jr[2];
@@ -432,12 +523,20 @@ PSATD_HD void psatd_point(T* vr, T* vi /* E0 E1 E2 B0 B1 B2 J0 J1 J2 */, double 
   }
 }
 
+// Eqs. PSATD_1 / PSATD_2 at one k-point: the coefficients (FP64, rounded to T
+// once), then the multiply-adds in T.
+template <typename T, bool INC = false>
+PSATD_HD void psatd_point(T* vr, T* vi /* E0 E1 E2 B0 B1 B2 J0 J1 J2 */, double kx, double ky,
+                          double kz, double c, double dt) {
+  const double rc = 1.0 / c;  // uniform: hoisted out of the k-point loop
+  update_apply<T>(vr, vi, update_coef<T, INC>(kx, ky, kz, c, rc, dt));
+}
+
 template <typename T>
 struct UpdArgs {
   Tables<T> t;
   const int32_t* items;  // prefix over boxes of ceil(P[1] H / PB)
   cx<T>* spec;
-  int64_t slab;
   int64_t sbias;
   UpdConst k;
 };
@@ -461,13 +560,13 @@ PSATD_HD void body_z_update(const UpdArgs<T>& a, int item, int tid, int nt, cx<T
   int32_t* kzi = reinterpret_cast<int32_t*>(twz + Pz);  // frequency at each z slot
   const cx<T>* gtz = a.t.tw + plz->tw;
   for (int i = tid; i < Pz; i += nt) kzi[i] = plan_index(plz, i);
-  const cx<T>* src = a.spec + (bx.soff - a.sbias) + q0;
-  const int64_t slab = a.slab;
+  const cx<T>* src = spec_at(a.spec, bx, a.sbias, 0) + q0;
+  const int64_t slab = bx.svol;  // field stride
   for (int i = tid; i < Pz; i += nt) twz[i] = gtz[i];
   // a full tile whose pencil runs start at even offsets moves two neighbouring
   // pencils per access
   const bool pairs = (PB % 2) == 0 && np == PB &&
-                     (((int64_t)nq | slab | (int64_t)(bx.soff - a.sbias + q0)) & 1) == 0;
+                     (((int64_t)nq | slab | (int64_t)(9 * (bx.soff - a.sbias) + q0)) & 1) == 0;
   if (pairs) {
     copy_grid3<4, Pair<cx<T>>>(9, Pz, PB / 2, tid, nt,
         [&](int, int f, int z, int p2) {
@@ -505,8 +604,7 @@ PSATD_HD void body_z_update(const UpdArgs<T>& a, int item, int tid, int nt, cx<T
     const int q = q0 + p;
     const int ky = (int)fdiv((uint32_t)q, dH);
     const int kx = q - ky * H;
-    psatd_point<T, INC, std::is_same<Eng, FftValu>::value>(vr, vi, kxt[kx], kyt[ky], kzt[kzi[slot]], a.k.c,
-                                                           a.k.dt);
+    psatd_point<T, INC>(vr, vi, kxt[kx], kyt[ky], kzt[kzi[slot]], a.k.c, a.k.dt);
 #pragma unroll
     for (int f = 0; f < 6; ++f) row[f * PB] = cx<T>{vr[f], vi[f]};
   }
@@ -516,7 +614,7 @@ PSATD_HD void body_z_update(const UpdArgs<T>& a, int item, int tid, int nt, cx<T
   // only the interior z-planes: the inverse pass reads nothing else (the guard
   // planes of E and B are rewritten by the exchange)
   const int gz = bx.g[2];
-  cx<T>* dst = a.spec + (bx.soff - a.sbias) + q0 + (int64_t)gz * nq;
+  cx<T>* dst = spec_at(a.spec, bx, a.sbias, 0) + q0 + (int64_t)gz * nq;
   const cx<T>* res = lds + gz * W;
   if (pairs) {
     copy_grid3<4, Pair<cx<T>>>(6, bx.n[2], PB / 2, tid, nt,
@@ -566,7 +664,7 @@ PSATD_HD void body_z_heat(const HeatArgs<T>& a, int item, int tid, int nt, cx<T>
   int32_t* kzi = reinterpret_cast<int32_t*>(twz + Pz);
   const cx<T>* gtz = a.t.tw + plz->tw;
   for (int i = tid; i < Pz; i += nt) kzi[i] = plan_index(plz, i);
-  cx<T>* col = a.spec + bx.soff + q0;
+  cx<T>* col = spec_at(a.spec, bx, 0, 0) + q0;
   const int ndata = Pz * PB;
   copy_batched<8, cx<T>>(ndata + Pz, tid, nt,
       [&](int i) {
@@ -614,7 +712,6 @@ struct InvArgs {
   Tables<T> t;
   const int32_t* items;  // prefix over boxes of n[2] * 6
   const cx<T>* spec;
-  int64_t slab;
   int64_t sbias;
   T* out[6];
   const PushBlk* push;       // fused E,B guard exchange (null: a separate fill pass)
@@ -652,7 +749,7 @@ PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>*
   bar();
 
   // half-spectrum rows (ky natural) -> LDS rows in stage-digit order along y
-  const cx<T>* src = a.spec + f * a.slab + (bx.soff - a.sbias) + (int64_t)z * Py * H;
+  const cx<T>* src = spec_at(a.spec, bx, a.sbias, f) + (int64_t)z * Py * H;
   for (int i = tid; i < Py + Nh + Px; i += nt)  // twy, twx, twr are contiguous
     twy[i] = i < Py ? gty[i] : (i < Py + Nh ? gtx[i - Py] : gtr[i - Py - Nh]);
   // FP32: two spectrum entries per access (measured slower in FP64)
@@ -765,7 +862,6 @@ struct SplitArgs {
   const T* in[9];      // x forward: field inputs
   T* out[6];           // x inverse: field outputs
   cx<T>* spec;
-  int64_t slab;
   int64_t sbias;
   const PushBlk* push;       // x inverse: fused E,B guard exchange (or null)
   const int32_t* push_off;
@@ -814,7 +910,7 @@ PSATD_HD void body_x_fwd(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>
   eng.template dit<-1, MAXR>(lds, ny, ld, 1, plx, twx, tid, nt, bar);
   pair_pass_rows<true>(lds, ny, ld, Nh, twr, tid, nt);
   bar();
-  cx<T>* dst = a.spec + f * a.slab + (bx.soff - a.sbias) + ((int64_t)z * Py + y0) * H;
+  cx<T>* dst = spec_at(a.spec, bx, a.sbias, f) + ((int64_t)z * Py + y0) * H;
   const FastDiv dH = make_fastdiv((uint32_t)H);
   copy_batched<8, cx<T>>(ny * H, tid, nt,
                          [&](int i) {
@@ -846,7 +942,7 @@ PSATD_HD void body_y(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>* ld
   int32_t* posy = reinterpret_cast<int32_t*>(twy + Py);
   for (int i = tid; i < Py; i += nt) posy[i] = plan_pos(ply, i);
   bar();
-  cx<T>* col = a.spec + f * a.slab + (bx.soff - a.sbias) + (int64_t)z * Py * H + c0;
+  cx<T>* col = spec_at(a.spec, bx, a.sbias, f) + (int64_t)z * Py * H + c0;
   const cx<T>* gty = a.t.tw + ply->tw;
   const int ntot = Py * kCB;
   copy_batched<8, cx<T>>(ntot + Py, tid, nt,
@@ -902,7 +998,7 @@ PSATD_HD void body_x_inv(const SplitArgs<T>& a, int item, int tid, int nt, cx<T>
   cx<T>* twr = twx + Nh;
   int32_t* posx = reinterpret_cast<int32_t*>(twr + Px);
   for (int i = tid; i < Nh; i += nt) posx[i] = plan_pos(plx, i);
-  const cx<T>* src = a.spec + f * a.slab + (bx.soff - a.sbias) + ((int64_t)z * Py + y0) * H;
+  const cx<T>* src = spec_at(a.spec, bx, a.sbias, f) + ((int64_t)z * Py + y0) * H;
   const cx<T>* gtx = a.t.tw + plx->tw;
   const cx<T>* gtr = a.t.tw + bx.twr;
   const int nrow = ny * H;

@@ -10,6 +10,7 @@
 
 #include "mfma_dft.hpp"
 #include "psatd_launch.hpp"
+#include "zreg.hpp"
 
 namespace psatd {
 
@@ -69,12 +70,28 @@ __global__ __launch_bounds__(NT) void k_inv_xy(InvArgs<T> a, int item0, int nite
   }
 }
 
+// FP32: at most 128 VGPRs, so that two 512-thread tiles share a CU (four
+// waves per SIMD); FP64 tiles measured slower when held to that budget.
 template <typename T, int NT, int PB, bool INC, int MAXR, int SPL>
-__global__ __launch_bounds__(NT) void k_z_update(UpdArgs<T> a, int item0, int nitems, int remap) {
+__global__ __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1) void k_z_update(UpdArgs<T> a, int item0, int nitems,
+                                                                          int remap) {
   cx<T>* lds = reinterpret_cast<cx<T>*>(psatd_lds);
   for (int it = first_item(remap); it < nitems; it += gridDim.x) {
     body_z_update<T, PB, INC, MAXR>(a, item0 + it, threadIdx.x, NT, lds, BlockBarrier{},
                                     typename EngOf<SPL>::type{});
+    __syncthreads();
+  }
+}
+
+// Register z pass (FP32 forms, padded z length N).  The VGPR budget keeps
+// at least MINW waves per SIMD resident.
+template <int N, int L, int W, int MINW>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MINW)))
+void k_z_reg(UpdArgs<float> a, const int32_t* items, int nitems, int remap) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds_raw[ZReg<N, L, W>::LDS_BYTES];
+  cx<float>* lds = reinterpret_cast<cx<float>*>(lds_raw);
+  for (int it = first_item(remap); it < nitems; it += gridDim.x) {
+    body_z_reg<N, L, W>(a, items, it, threadIdx.x, lds);
     __syncthreads();
   }
 }
@@ -297,7 +314,6 @@ static hipError_t fwd_t(const DevPlan& p, const Batch& b, void* const* in9, void
   a.nfield = scalar ? 1 : 9;
   for (int f = 0; f < 9; ++f) a.in[f] = (f < a.nfield) ? reinterpret_cast<const T*>(in9[f]) : nullptr;
   a.spec = reinterpret_cast<cx<T>*>(spec);
-  a.slab = p.slab;
   a.sbias = b.sbias;
   const int g = grid_for(b.nF, p.grid_cap[kPhaseFwd]);
   if (!g) return hipSuccess;
@@ -343,7 +359,6 @@ static hipError_t upd_t(const DevPlan& p, const Batch& b, void* spec, hipStream_
   a.t = tables<T>(p);
   a.items = p.itemsU;
   a.spec = reinterpret_cast<cx<T>*>(spec);
-  a.slab = p.slab;
   a.sbias = b.sbias;
   a.k.c = p.c;
   a.k.dt = p.dt;
@@ -359,6 +374,42 @@ static hipError_t upd_t(const DevPlan& p, const Batch& b, void* spec, hipStream_
 
 hipError_t launch_upd(const DevPlan& p, const Batch& b, void* spec, hipStream_t st) {
   return p.f64 ? upd_t<double>(p, b, spec, st) : upd_t<float>(p, b, spec, st);
+}
+
+template <int N, int L, int W, int MINW>
+static hipError_t zreg_go(const UpdArgs<float>& a, const int32_t* items, int n, int cap, int remap,
+                          hipStream_t st) {
+  const int g = grid_for(n, cap);
+  if (!g) return hipSuccess;
+  hipLaunchKernelGGL((k_z_reg<N, L, W, MINW>), dim3(g), dim3(64 * W), 0, st, a, items, n, remap);
+  return hipGetLastError();
+}
+
+// One launch per group of boxes sharing a padded z length (every box of the
+// plan belongs to a group with a register schedule, see zreg_schedule).
+hipError_t launch_upd_reg(const DevPlan& p, void* spec, hipStream_t st) {
+  UpdArgs<float> a;
+  a.t = tables<float>(p);
+  a.items = nullptr;
+  a.spec = reinterpret_cast<cx<float>*>(spec);
+  a.sbias = 0;
+  a.k.c = p.c;
+  a.k.dt = p.dt;
+  const int cap = p.grid_cap[kPhaseUpd];
+  for (int i = 0; i < p.nzg; ++i) {
+    const ZGroup& zg = p.zg[i];
+    const int32_t* items = p.itemsZR + zg.off;
+    hipError_t e = hipErrorInvalidValue;
+    switch (zg.N) {
+#define PSATD_ZREG_CASE(N_, L_, W_, MINW_) \
+  case N_: e = zreg_go<N_, L_, W_, MINW_>(a, items, zg.n, cap, p.xcd, st); break;
+      PSATD_ZREG_SHAPES(PSATD_ZREG_CASE)
+#undef PSATD_ZREG_CASE
+      default: break;
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template <typename T, int NT, int MAXR, int SPL>
@@ -379,7 +430,6 @@ static hipError_t inv_t(const DevPlan& p, const Batch& b, const void* spec, void
   a.t = tables<T>(p);
   a.items = scalar ? p.itemsN : p.itemsI;  // one field: n[2] planes per box
   a.spec = reinterpret_cast<const cx<T>*>(spec);
-  a.slab = p.slab;
   a.sbias = b.sbias;
   for (int f = 0; f < 6; ++f) a.out[f] = (f == 0 || !scalar) ? reinterpret_cast<T*>(out6[f]) : nullptr;
   a.push = (p.fuse && !scalar) ? p.push : nullptr;
@@ -445,7 +495,6 @@ static SplitArgs<T> split_args(const DevPlan& p, void* spec) {
   for (int f = 0; f < 9; ++f) a.in[f] = nullptr;
   for (int f = 0; f < 6; ++f) a.out[f] = nullptr;
   a.spec = reinterpret_cast<cx<T>*>(spec);
-  a.slab = p.slab;
   a.sbias = 0;
   a.push = p.fuse ? p.push : nullptr;
   a.push_off = p.fuse ? p.push_off : nullptr;

@@ -50,6 +50,10 @@ struct DevPlan {
   int64_t slab;              // complex elements of one spectral field slab
   double c, dt;
   int32_t grid_cap[kNumPhases];  // 0: one work-group per item; else persistent grid
+  int32_t zreg;                  // 1: the z pass runs the register kernels (groups below)
+  int32_t nzg;
+  ZGroup zg[kMaxZGroups];
+  const int32_t* itemsZR;
 };
 
 hipError_t launch_fill(const DevPlan& p, void* const* comps, int ncomp, hipStream_t st);
@@ -57,6 +61,8 @@ hipError_t launch_sum(const DevPlan& p, void* const* J, hipStream_t st);
 hipError_t launch_fwd(const DevPlan& p, const Batch& b, void* const* in9, void* spec, hipStream_t st,
                       bool scalar = false);
 hipError_t launch_upd(const DevPlan& p, const Batch& b, void* spec, hipStream_t st);
+// the z pass with the z transforms in registers (all boxes, FP32 VALU form)
+hipError_t launch_upd_reg(const DevPlan& p, void* spec, hipStream_t st);
 hipError_t launch_inv(const DevPlan& p, const Batch& b, const void* spec, void* const* out6, hipStream_t st,
                       bool scalar = false);
 // heat equation (Sec. 5): z pass of one field with the exp(-D |[k]|^2 dt) propagator

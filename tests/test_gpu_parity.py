@@ -652,3 +652,21 @@ def test_autotune_and_profiled_run_sum_deposited_currents_once(tmp_path):
     say(f"  after autotune + 3 profiled steps: rel-L2 E {eE} B {eB}")
     assert max(eE + eB) <= TOL64
     assert max(boxes_rel_l2(case.boxes(case.J), oJ3)) <= 1e-14
+
+
+@pytest.mark.parametrize("z_reg", [1, 0])
+def test_register_z_pass_two_shapes_ragged_tile(z_reg):
+    """The FP32 z pass with the z transforms in registers (z_reg=1) and the
+    LDS-staged one (z_reg=0) on two box shapes that share a padded z length
+    of 96 (padded 96^3 and 88x96x96: the second box's pencil count 96 x 45 is
+    not a multiple of the register tile), against the oracle, 3 steps."""
+    say(f"register z pass, two shapes, ragged tile, z_reg={z_reg}")
+    N = (144, 96, 64)
+    lo = np.array([[0, 0, 0], [64, 0, 0]])
+    n = np.array([[64, 96, 64], [80, 96, 64]])
+    g = np.array([[16, 0, 16], [4, 0, 16]])
+    fields = random_fields(N, 51, p=16)
+    case, eE, eB, _ = run_both(N, lo, n, g, 16, 0.5, 1.0, "f32", "replicated", fields, 3,
+                               tuning=dict(z_reg=z_reg))
+    assert [case.plan.layout(s)[0] for s in range(2)] == [(96, 96, 96), (88, 96, 96)]
+    check(case, eE, eB, "f32", TOL32)
