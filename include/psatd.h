@@ -113,7 +113,12 @@ typedef enum {
   PSATD_TUNE_Z_REG = 12,      /* 1: the FP32 VALU z pass holds each z transform in registers (compiled
                                  padded z lengths only, unbatched plans); 0 (default, faster on 96^3 and
                                  176^3 boxes): the LDS-staged z pass */
-  PSATD_NTUNE = 13
+  PSATD_TUNE_PULL_EB = 13,    /* 1 (default for unbatched plans whose planes fit the LDS): within a run the
+                                 forward pass reads every E, B guard cell from the subdomain that owns it,
+                                 so the E,B guard exchange runs once, after the run's last step (the state
+                                 is consistent again on return, and every value is the one the exchange
+                                 would have copied); 0: the exchange after every step */
+  PSATD_NTUNE = 14
 } psatd_tune_key;
 
 /*

@@ -42,6 +42,9 @@ struct HostTables {
   std::vector<int32_t> itemsG;    // guard fill: prefix over pieces of their z extent
   std::vector<int32_t> pieceOf;   // guard fill: item -> piece
   bool fuse_eb = false;           // E,B guards written by the inverse pass
+  std::vector<PullPiece> pullp;   // guard regions per destination box, for the forward pass
+  std::vector<int32_t> pull_off;  // nsub + 1
+  bool pull_eb = false;           // the forward pass reads E,B guard cells from their owners
   int ldsX = 0, ldsY = 0;
   std::vector<Batch> batches;
   int64_t batch_slab = 0;     // complex elements of one spectral field slab of the largest batch
@@ -352,6 +355,28 @@ inline void build_push(HostTables& h) {
     f.vec = (k.lx % V == 0 && f.so % V == 0 && f.dof % V == 0 && f.sP0 % V == 0 && f.dP0 % V == 0 &&
              f.sPl % V == 0 && f.dPl % V == 0);
     h.fillp.push_back(f);
+  }
+  // the same pieces by destination box, as the forward pass pulls them
+  h.pullp.clear();
+  h.pull_off.assign(h.nsub + 1, 0);
+  for (int d = 0; d < h.nsub; ++d) {
+    for (size_t i = 0; i < h.push.size(); ++i) {
+      const PushBlk& k = h.push[i];
+      if (k.dst != d) continue;
+      const BoxD& sb = h.box[k.src];
+      PullPiece q{};
+      q.so = h.fillp[i].so;
+      q.sPl = sb.P[0] * sb.P[1];
+      q.sP0 = sb.P[0];
+      q.qz = k.qz;
+      q.lz = k.lz;
+      q.qy = k.qy;
+      q.ly = k.ly;
+      q.qx = k.qx;
+      q.lx = k.lx;
+      h.pullp.push_back(q);
+    }
+    h.pull_off[d + 1] = (int32_t)h.pullp.size();
   }
   // work list of the guard fill: one item per z-plane of every piece
   h.itemsG.assign(h.push.size() + 1, 0);

@@ -71,7 +71,7 @@ struct psatd_plan_s {
   int device = 0;
   void* blob = nullptr;  // device tables
   int32_t* d_itemsU = nullptr;  // z-update work list (depends on the z tile)
-  int32_t tune[PSATD_NTUNE] = {0, 1, 0, 0, 0, 0, 0, 16, 256, 512, 0, 1, 0};
+  int32_t tune[PSATD_NTUNE] = {0, 1, 0, 0, 0, 0, 0, 16, 256, 512, 0, 1, 0, 0};
   void* ws = nullptr;
   int64_t ws_bytes = 0;
   bool ws_owned = false;
@@ -156,8 +156,11 @@ psatd_status check_fields(psatd_plan_t p, void* const* v, int count, const char*
 // first: the first step since J was (re)deposited or changed.  J is read-only
 // in the step, so its guard exchange (sum and/or fill) is needed only then;
 // later steps of a run with J held fixed find it already consistent.
+// last: the run's last step.  With the pulled E,B exchange the guard copies
+// are refreshed only then (every forward pass of the run reads guard cells
+// from their owners), so the state is consistent again on return.
 psatd_status enqueue_step(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3],
-                          hipStream_t st, bool first,
+                          hipStream_t st, bool first, bool last,
                           std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>* prof = nullptr,
                           void* ws = nullptr) {
   const DevPlan& d = p->dp;
@@ -211,7 +214,7 @@ psatd_status enqueue_step(psatd_plan_t p, void* const E[3], void* const B[3], vo
     PSATD_MARK(kPhaseInv, false);
   }
   PSATD_MARK(kPhaseExchEB, true);
-  if (!d.fuse) HIPCHK(p, launch_fill(d, eb, 6, st));  // fused: written by the inverse pass
+  if (!d.fuse && (!d.pull || last)) HIPCHK(p, launch_fill(d, eb, 6, st));  // fused: written by the inverse pass
   PSATD_MARK(kPhaseExchEB, false);
 #undef PSATD_MARK
   return PSATD_OK;
@@ -323,6 +326,8 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   const size_t o_fp = reserve(std::max<size_t>(h.fillp.size(), 1) * sizeof(FillPiece));
   const size_t o_pOf = reserve(std::max<size_t>(h.pieceOf.size(), 1) * 4);
   const size_t o_iZR = reserve(std::max<size_t>(h.itemsZR.size(), 1) * 4);
+  const size_t o_pull = reserve(std::max<size_t>(h.pullp.size(), 1) * sizeof(PullPiece));
+  const size_t o_poff = reserve(h.pull_off.size() * 4);
   std::vector<unsigned char> hb(total, 0);
   auto put = [&](size_t off, const void* src, size_t bytes) {
     if (bytes) std::memcpy(hb.data() + off, src, bytes);
@@ -350,6 +355,8 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   put(o_fp, h.fillp.data(), h.fillp.size() * sizeof(FillPiece));
   put(o_pOf, h.pieceOf.data(), h.pieceOf.size() * 4);
   put(o_iZR, h.itemsZR.data(), h.itemsZR.size() * 4);
+  put(o_pull, h.pullp.data(), h.pullp.size() * sizeof(PullPiece));
+  put(o_poff, h.pull_off.data(), h.pull_off.size() * 4);
   if ((e = hipMalloc(&p->blob, total)) != hipSuccess) return hipfail(e, "hipMalloc(tables)");
   if ((e = hipMemcpy(p->blob, hb.data(), total, hipMemcpyHostToDevice)) != hipSuccess)
     return hipfail(e, "hipMemcpy(tables)");
@@ -408,10 +415,15 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   d.nzg = (int32_t)h.zgroups.size();
   for (int i = 0; i < d.nzg; ++i) d.zg[i] = h.zgroups[i];
   d.zreg = 0;  // opt-in: measured slower than the LDS-staged z pass on 96^3 and 176^3 boxes
+  d.pullp = reinterpret_cast<const PullPiece*>(B + o_pull);
+  d.pull_off = reinterpret_cast<const int32_t*>(B + o_poff);
+
   p->tune[PSATD_TUNE_Z_REG] = d.zreg;
   d.fuse = (h.fuse_eb && h.batches.size() == 1) ? 1 : 0;
   d.spl = h.spl;
   p->tune[PSATD_TUNE_FUSE_EB] = d.fuse;
+  d.pull = (!h.split && !d.fuse && h.batches.size() == 1) ? 1 : 0;
+  p->tune[PSATD_TUNE_PULL_EB] = d.pull;
   d.nF = h.itemsF.back();
   d.nU = h.itemsU.back();
   d.nI = h.itemsI.back();
@@ -479,7 +491,7 @@ psatd_status psatd_set_workspace(psatd_plan_t p, void* dev, int64_t bytes) {
 psatd_status psatd_step(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3]) {
   psatd_status r = check_step_args(p, E, B, J);
   if (r != PSATD_OK) return r;
-  return enqueue_step(p, E, B, J, p->stream, true);
+  return enqueue_step(p, E, B, J, p->stream, true, true);
 }
 
 psatd_status psatd_step_noalloc(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3]) {
@@ -495,7 +507,7 @@ psatd_status psatd_step_noalloc(psatd_plan_t p, void* const E[3], void* const B[
                     std::to_string(kScratchBytes) + " bytes; batch the boxes (PSATD_TUNE_BATCH_BOXES)");
   void* ws = scratch_of(p->device);
   if (!ws) return fail(p, PSATD_E_STATE, "static scratch not resolved on the plan's device");
-  return enqueue_step(p, E, B, J, p->stream, true, nullptr, ws);
+  return enqueue_step(p, E, B, J, p->stream, true, true, nullptr, ws);
 }
 
 psatd_status psatd_run(psatd_plan_t p, void* const E[3], void* const B[3], void* const J[3],
@@ -516,7 +528,7 @@ psatd_status psatd_run(psatd_plan_t p, void* const E[3], void* const B[3], void*
     HIPCHK(p, hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed));
     psatd_status er = PSATD_OK;
     for (int i = 0; i < nsteps && er == PSATD_OK; ++i)
-      er = enqueue_step(p, E, B, J, p->cap_stream, i == 0);
+      er = enqueue_step(p, E, B, J, p->cap_stream, i == 0, i == nsteps - 1);
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
     if (er != PSATD_OK) {
@@ -585,7 +597,7 @@ psatd_status run_profiled(psatd_plan_t p, void* const E[3], void* const B[3], vo
   for (int stp = 0; stp < nsteps && out == PSATD_OK; ++stp) {
     const bool first = exchange_J && stp == 0;
     const size_t used = first ? npairs : npairs - 1;  // pairs recorded by this step
-    out = enqueue_step(p, E, B, J, p->stream, first, &ev);
+    out = enqueue_step(p, E, B, J, p->stream, first, stp == nsteps - 1, &ev);
     if (out != PSATD_OK) break;
     if (hipEventSynchronize(ev[used - 1].second.second) != hipSuccess) { out = fail(p, PSATD_E_HIP, "hipEventSynchronize"); break; }
     for (size_t i = 0; i < used; ++i) {
@@ -670,6 +682,10 @@ psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
       if (value && p->h.batches.size() > 1) return fail(p, PSATD_E_INVALID, "the split passes do not batch");
       p->h.split = value != 0;
       d.split = value;
+      if (value) {  // the split x pass reads its rows in place
+        d.pull = 0;
+        p->tune[PSATD_TUNE_PULL_EB] = 0;
+      }
       break;
     }
     case PSATD_TUNE_BATCH_BOXES: {
@@ -683,6 +699,8 @@ psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
         p->h.fuse_eb = false;
         d.fuse = 0;
         p->tune[PSATD_TUNE_FUSE_EB] = 0;
+        d.pull = 0;  // and its owners' old interiors
+        p->tune[PSATD_TUNE_PULL_EB] = 0;
       }
       break;
     }
@@ -692,6 +710,17 @@ psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
         return fail(p, PSATD_E_INVALID, "the fused E,B exchange needs all boxes in one batch");
       p->h.fuse_eb = value != 0;
       d.fuse = value;
+      if (value) {  // the inverse pass keeps every guard copy current
+        d.pull = 0;
+        p->tune[PSATD_TUNE_PULL_EB] = 0;
+      }
+      break;
+    }
+    case PSATD_TUNE_PULL_EB: {
+      if (value != 0 && value != 1) return fail(p, PSATD_E_INVALID, "pull_eb must be 0 or 1");
+      if (value && (p->h.batches.size() > 1 || d.split || d.fuse))
+        return fail(p, PSATD_E_INVALID, "the pulled E,B exchange needs one batch, unsplit x/y passes and no fused exchange");
+      d.pull = value;
       break;
     }
     case PSATD_TUNE_Z_REG:
@@ -737,7 +766,7 @@ psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
       break;
     default: {
       if (value < 0) return fail(p, PSATD_E_INVALID, "grid size must be >= 0");
-      static const int phase_of[] = {0, 0, kPhaseFwd, kPhaseUpd, kPhaseInv, kPhaseExchEB, 0, 0, 0, 0, 0, 0, 0};
+      static const int phase_of[] = {0, 0, kPhaseFwd, kPhaseUpd, kPhaseInv, kPhaseExchEB, 0, 0, 0, 0, 0, 0, 0, 0};
       d.grid_cap[phase_of[key]] = value;
       if (key == PSATD_TUNE_GRID_EXCH) d.grid_cap[kPhaseExchJ] = value;
     }

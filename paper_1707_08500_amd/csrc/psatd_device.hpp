@@ -306,6 +306,17 @@ PSATD_HD void push_guards(const PushBlk* blk, int b0, int b1, const BoxD* boxes,
 // ------------------------------------------------------------------ pass F
 // Forward R2C along x and C2C along y of one z-plane of one field of one box.
 // Output: half spectrum plane [ky][kx] (kx = 0..H-1) in natural order.
+// A guard region of a destination box seen from the box that owns it: the
+// padded cells [qz, qz+lz) x [qy, qy+ly) x [qx, qx+lx) of the destination are
+// the source's interior cells starting at element `so` (plane 0, row 0,
+// column 0) with the source's plane and row pitches.  Every guard cell of a
+// box lies in exactly one of its pull pieces.
+struct PullPiece {
+  int64_t so;
+  int32_t sPl, sP0;
+  int32_t qz, lz, qy, ly, qx, lx;
+};
+
 template <typename T>
 struct FwdArgs {
   Tables<T> t;
@@ -314,7 +325,50 @@ struct FwdArgs {
   const T* in[9];
   cx<T>* spec;             // spectral workspace (box-major, see spec_at)
   int64_t sbias;           // spectral offset of the first box held by spec
+  // Fields f < npull read their guard cells from the owners (pull pieces of
+  // box s: pull[pull_off[s] .. pull_off[s+1])) instead of the box's own,
+  // possibly stale, guard copies; npull = 0 reads every padded cell in place.
+  int32_t npull;
+  const PullPiece* pull;
+  const int32_t* pull_off;
 };
+
+// Copies a rectangle of real cells src[r * sP0 + c] (r < ly, c < lx) into the
+// LDS plane whose x rows are packed as complex pairs in stage-digit order:
+// cell (y0 + r, x0 + c) goes to float 2 posx[(x0 + c) / 2] + (x0 + c) % 2 of
+// row y0 + r.  Four cells per access when the rectangle and the source are
+// 16-byte aligned, two when 8-byte aligned, else one.
+template <typename T>
+PSATD_HD void copy_rect_to_plane(const T* src, int sP0, int ly, int lx, int y0, int x0, cx<T>* lds, int ld,
+                                 const int32_t* posx, int tid, int nt) {
+  T* ldsT = reinterpret_cast<T*>(lds);
+  const uintptr_t sa = reinterpret_cast<uintptr_t>(src);
+  if (sizeof(T) == 4 && ((x0 | lx | sP0) & 3) == 0 && (sa & 15) == 0) {
+    using Q = Pair<Pair<T>>;
+    copy_grid<4, Q>(ly, lx >> 2, tid, nt,
+                    [&](int, int r, int c4) { return *reinterpret_cast<const Q*>(src + (int64_t)r * sP0 + 4 * c4); },
+                    [&](int, int r, int c4, Q v) {
+                      cx<T>* row = lds + (y0 + r) * ld;
+                      const int h = (x0 >> 1) + 2 * c4;
+                      row[posx[h]] = cx<T>{v.a.a, v.a.b};
+                      row[posx[h + 1]] = cx<T>{v.b.a, v.b.b};
+                    });
+  } else if (((x0 | lx | sP0) & 1) == 0 && (sa % sizeof(Pair<T>)) == 0) {
+    copy_grid<8, Pair<T>>(ly, lx >> 1, tid, nt,
+                          [&](int, int r, int c2) {
+                            return *reinterpret_cast<const Pair<T>*>(src + (int64_t)r * sP0 + 2 * c2);
+                          },
+                          [&](int, int r, int c2, Pair<T> v) {
+                            lds[(y0 + r) * ld + posx[(x0 >> 1) + c2]] = cx<T>{v.a, v.b};
+                          });
+  } else {
+    copy_grid<8, T>(ly, lx, tid, nt, [&](int, int r, int c) { return src[(int64_t)r * sP0 + c]; },
+                    [&](int, int r, int c, T v) {
+                      const int x = x0 + c;
+                      ldsT[2 * ((y0 + r) * ld + posx[x >> 1]) + (x & 1)] = v;
+                    });
+  }
+}
 
 // LDS: the plane [y][x] with row stride ld, then the twiddles of the x plan
 // (Nh), the y plan (Py) and W_Px (real <-> half spectrum).
@@ -349,7 +403,32 @@ PSATD_HD void body_fwd_xy(const FwdArgs<T>& a, int item, int tid, int nt, cx<T>*
   const cx<T>* src = reinterpret_cast<const cx<T>*>(a.in[f] + bx.foff + (int64_t)z * Py * Px);
   for (int i = tid; i < Nh + Py + Px; i += nt)  // twx, twy, twr are contiguous
     twx[i] = i < Nh ? gtx[i] : (i < Nh + Py ? gty[i - Nh] : gtr[i - Nh - Py]);
-  if ((Nh & 1) == 0 && (reinterpret_cast<uintptr_t>(src) % sizeof(Pair<cx<T>>)) == 0) {
+  if (f < a.npull) {
+    // The box's own interior cells, then every guard region of this plane
+    // from the box that owns it (Fig. 3 step 3 fused into the next push).
+    // The waves share the rectangles (the interior in one row band per wave,
+    // the pieces that meet the plane dealt round-robin), each copying its own
+    // with its 64 lanes, so their memory round trips overlap.
+    const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+    const int gx = bx.g[0], gy = bx.g[1], gz = bx.g[2];
+    const T* inf = a.in[f];
+    int dealt = 0;
+    if (z >= gz && z < gz + bx.n[2]) {
+      const int ny = bx.n[1];
+      const int r0 = (int)(((int64_t)ny * wave) / nw), r1 = (int)(((int64_t)ny * (wave + 1)) / nw);
+      if (r1 > r0)
+        copy_rect_to_plane<T>(inf + bx.foff + ((int64_t)z * Py + gy + r0) * Px + gx, Px, r1 - r0, bx.n[0], gy + r0,
+                              gx, lds, ld, posx, lane, 64);
+      dealt = nw;
+    }
+    for (int b = a.pull_off[s]; b < a.pull_off[s + 1]; ++b) {
+      const PullPiece k = a.pull[b];
+      if (z < k.qz || z >= k.qz + k.lz) continue;
+      if (dealt++ % nw != wave) continue;
+      copy_rect_to_plane<T>(inf + k.so + (int64_t)(z - k.qz) * k.sPl, k.sP0, k.ly, k.lx, k.qy, k.qx, lds, ld, posx,
+                            lane, 64);
+    }
+  } else if ((Nh & 1) == 0 && (reinterpret_cast<uintptr_t>(src) % sizeof(Pair<cx<T>>)) == 0) {
     // two neighbouring complex values per access (rows of even length)
     const Pair<cx<T>>* src2 = reinterpret_cast<const Pair<cx<T>>*>(src);
     copy_grid<4, Pair<cx<T>>>(Py, Nh >> 1, tid, nt, [&](int i, int, int) { return src2[i]; },

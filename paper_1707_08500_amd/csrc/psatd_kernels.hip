@@ -312,6 +312,9 @@ static hipError_t fwd_t(const DevPlan& p, const Batch& b, void* const* in9, void
   a.t = tables<T>(p);
   a.items = scalar ? p.itemsP : p.itemsF;  // one field: P[2] planes per box
   a.nfield = scalar ? 1 : 9;
+  a.npull = (p.pull && !scalar) ? 6 : 0;
+  a.pull = p.pullp;
+  a.pull_off = p.pull_off;
   for (int f = 0; f < 9; ++f) a.in[f] = (f < a.nfield) ? reinterpret_cast<const T*>(in9[f]) : nullptr;
   a.spec = reinterpret_cast<cx<T>*>(spec);
   a.sbias = b.sbias;

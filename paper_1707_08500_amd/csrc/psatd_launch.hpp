@@ -50,6 +50,9 @@ struct DevPlan {
   int64_t slab;              // complex elements of one spectral field slab
   double c, dt;
   int32_t grid_cap[kNumPhases];  // 0: one work-group per item; else persistent grid
+  int32_t pull;                  // 1: the forward pass pulls E,B guard cells from their owners
+  const PullPiece* pullp;
+  const int32_t* pull_off;
   int32_t zreg;                  // 1: the z pass runs the register kernels (groups below)
   int32_t nzg;
   ZGroup zg[kMaxZGroups];

@@ -462,7 +462,7 @@ def test_launch_shapes_do_not_change_results(tmp_path):
     ref = None
     settings = [dict(), dict(max_radix=8), dict(xy_threads=512), dict(xy_threads=1024), dict(z_threads=1024),
                 dict(z_pencils=8), dict(xcd_remap=0), dict(fuse_eb=0), dict(batch_boxes=3),
-                dict(grid_fwd=100, grid_upd=64, grid_inv=96, grid_exch=50),
+                dict(grid_fwd=100, grid_upd=64, grid_inv=96, grid_exch=50), dict(fuse_eb=0, pull_eb=1),
                 dict(max_radix=8, xy_threads=512, z_threads=1024, batch_boxes=2)]
     for st in settings:
         for glob, pad in ((E, case.E), (B, case.B), (J, case.J)):
@@ -670,3 +670,36 @@ def test_register_z_pass_two_shapes_ragged_tile(z_reg):
                                tuning=dict(z_reg=z_reg))
     assert [case.plan.layout(s)[0] for s in range(2)] == [(96, 96, 96), (88, 96, 96)]
     check(case, eE, eB, "f32", TOL32)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16x6"])
+@pytest.mark.parametrize("shape", ["uneven", "96"])
+def test_pulled_eb_exchange_is_the_copy_pass(precision, shape):
+    """The forward pass reading E,B guard cells from their owners, with the
+    copy pass only after a run's last step (pull_eb=1), leaves exactly the
+    bytes of the copy pass after every step (pull_eb=0): uneven boxes with
+    odd guard widths wider than their neighbours (one-cell copies) and 96^3
+    boxes (16-byte copies), a 4-step graph run, a single step, a 2-step run."""
+    import torch
+    say(f"pulled E,B exchange vs copy pass, {precision}, {shape}")
+    if shape == "uneven":
+        N, lo, n, g = uneven_small()
+        p = 4
+    else:
+        N = (128, 64, 64)
+        lo, n, g = synth.uniform_decomposition(N, (2, 1, 1), 16)
+        p = 32
+    E, B, J = random_fields(N, 61, p=p)
+    out = []
+    for pull in (1, 0):
+        case = GpuCase(N, lo, n, g, p, 0.3, 1.0, precision, "deposited", E, B, J)
+        case.plan.set_tuning(pull_eb=pull)
+        assert case.plan.tuning()["pull_eb"] == pull
+        case.plan.run(case.E, case.B, case.J, 4)
+        case.plan.step(case.E, case.B, case.J)
+        case.plan.run(case.E, case.B, case.J, 2)
+        case.plan.sync()
+        out.append([x.cpu() for x in case.E + case.B + case.J])
+        case.plan.close()
+    for a, b in zip(*out):
+        assert torch.equal(a, b)
