@@ -79,11 +79,64 @@ def decomposition(wl):
 def global_modified_k(N, d, p):
     """The library's FP64 order-p modified wavenumbers of the global grid, per
     axis (a one-box plan without guards, read back through the C-ABI)."""
-    from paper_1707_08500_amd import psatd
-    plan = psatd.Plan(N, d, [[0, 0, 0]], [list(N)], [[0, 0, 0]], p, 0.5, precision="f32")
-    k = [plan.modified_k(0, u) for u in range(3)]
-    plan.close()
-    return k
+    from paper_1707_08500_amd import truncation
+    return truncation.global_modified_k(N, d, p)
+
+
+def field_diagnostics(final, inputs, kt, t_total, c=1.0, dev="cuda"):
+    """Physics diagnostics of a final state (six global components, any dtype,
+    on any device), in FP64 on the device with the global grid's order-p [k]
+    (Sec. 3.1):
+      energy     W = 1/2 sum(|E|^2 + c^2 |B|^2);
+      div_B_rel  |[k].B~| / | |[k]| B~ |, zero for PSATD-global up to rounding
+                 (the local method's guard truncation shows here);
+      gauss_rel  |[k].(E~(T) - E~(0)) + T [k].J~| / | |[k]| E~(T) |: with a
+                 constant J, Gauss's law and charge continuity make the
+                 longitudinal E change by -T J exactly under Eqs. PSATD_1/2."""
+    import torch
+    Nx, Ny, Nz = inputs.N
+    H = Nx // 2 + 1
+    f64 = torch.float64
+    kx = torch.tensor(kt[0][:H], dtype=f64, device=dev)[None, None, :]
+    ky = torch.tensor(kt[1], dtype=f64, device=dev)[None, :, None]
+    kz = torch.tensor(kt[2], dtype=f64, device=dev)[:, None, None]
+    K = (kx, ky, kz)
+    k2 = kx * kx + ky * ky + kz * kz
+    w = torch.full((H,), 2.0, dtype=f64, device=dev)  # half-spectrum weights of a real field
+    w[0] = 1.0
+    if Nx % 2 == 0:
+        w[-1] = 1.0
+    w = w[None, None, :]
+
+    def spec(x):
+        return torch.fft.rfftn(x.to(dev, f64).reshape(Nz, Ny, Nx))
+
+    def wsum(a):
+        return float(torch.sum(w * a))
+
+    energy = 0.0
+    for i, x in enumerate(final):
+        energy += 0.5 * (1.0 if i < 3 else c * c) * float(torch.sum(x.to(dev, f64) ** 2))
+    div = torch.zeros((Nz, Ny, H), dtype=torch.complex128, device=dev)
+    den_b = 0.0
+    for u in range(3):
+        b = spec(final[3 + u])
+        div += K[u] * b
+        den_b += wsum(k2 * b.abs() ** 2)
+        del b
+    div_b = math.sqrt(wsum(div.abs() ** 2) / den_b) if den_b else 0.0
+    E0, J = inputs.field("E", f64, dev), inputs.field("J", f64, dev)
+    res = torch.zeros_like(div)
+    den_e = 0.0
+    for u in range(3):
+        e = spec(final[u])
+        den_e += wsum(k2 * e.abs() ** 2)
+        res += K[u] * (e - spec(E0[u]) + t_total * spec(J[u]))
+        del e
+    gauss = math.sqrt(wsum(res.abs() ** 2) / den_e) if den_e else 0.0
+    del div, res, E0, J
+    torch.cuda.empty_cache()
+    return {"energy": energy, "div_B_rel": div_b, "gauss_rel": gauss}
 
 
 class DeviceInputs:
@@ -522,17 +575,21 @@ def batched_block(wl_name, forms, steps, warmup, profile_steps, autotune):
     inputs = DeviceInputs(wl, (1.0, 1.0, 1.0))
     out = {"workload": wl["desc"], "subdomains": len(dec[0]), "steps": steps, "forms": {}}
     ref = None
+    kt = global_modified_k(wl["N"], (1.0, 1.0, 1.0), wl["p"])
     for prec in ["f64"] + forms:
         res, plan = measure_form(wl_name, wl, dec, inputs, prec, steps, warmup, profile_steps,
                                  autotune=autotune, profile=prec != "f64")
         fin = res.pop("final")
         plan.close()
         entry = {k: res[k] for k in ("value", "ms_per_step", "phases_ms", "tuning") if k in res}
+        entry["diagnostics"] = field_diagnostics(fin, inputs, kt, steps * wl["dt"])
         if prec == "f64":
             ref = fin
             out["fp64_plain"] = entry
         else:
             entry["rel_l2_vs_fp64_after_k_steps"] = rel_l2(fin, ref)
+            e64 = out["fp64_plain"]["diagnostics"]["energy"]
+            entry["diagnostics"]["energy_rel_to_fp64"] = (entry["diagnostics"]["energy"] - e64) / e64
             entry["roofline"] = roofline_block(wl_name, res, prec, dec)
             entry["hbm_fraction_of_step"] = step_fractions(res, dec, 4)
             out["forms"][prec] = entry
@@ -658,6 +715,14 @@ def main():
             err[name] = float(torch.linalg.vector_norm(finals[prec][i] - ref)) / (den if den else 1.0)
         results[prec]["rel_l2_vs_fp64"] = err
         gate["forms"][prec] = {"max_rel_l2": max(err.values()), "passed": max(err.values()) <= GATE_TOL}
+    # physics diagnostics of every run's final state (reported, not gated)
+    kt = global_modified_k(N, d, wl["p"])
+    t_total = (gate_steps or args.steps) * wl["dt"]
+    diag = {prec: field_diagnostics(finals[prec], inputs, kt, t_total) for prec in finals}
+    if "f64" in diag:
+        for prec in forms:
+            diag[prec]["energy_rel_to_fp64"] = (diag[prec]["energy"] - diag["f64"]["energy"]) / diag["f64"]["energy"]
+    diag["after_steps"] = gate_steps or args.steps
     ok = [f for f in forms if gate["forms"].get(f, {}).get("passed")]
     gate["passed"] = bool(ok)
     if not ok:
@@ -689,6 +754,7 @@ def main():
         "roofline": roofline_block(args.workload, r32, head, dec),
         "fp32_forms": {f: {k: results[f][k] for k in ("value", "ms_per_step", "rel_l2_vs_fp64", "phases_ms")
                            if k in results[f]} for f in forms},
+        "diagnostics": diag,
     }
     if "f64" in results:
         r64 = results["f64"]

@@ -5,6 +5,7 @@ import os
 import sys
 
 import numpy as np
+import pytest
 
 sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 import bench  # noqa: E402
@@ -81,3 +82,39 @@ def test_roofline_block_is_bmin_over_the_dominant_kernel():
     assert abs(rf["kernel_own"]["achieved"] - algo["z_update"] / 1.25e-3 / 1e9) < 1e-6
     assert rf["traffic"] is None
     assert rf["kernel_instance"] == "psatd::k_z_update<float, 512, 8, true, 16, 0>"
+
+
+def test_field_diagnostics_vanish_on_oracle_steps_and_see_a_planted_error():
+    """The bench's div B and Gauss-law diagnostics (Sec. 3.1 with the
+    continuity of a constant J) read rounding-level zeros on states the oracle's
+    PSATD-global produced, and a longitudinal E error planted on the CPU shows."""
+    import torch
+    from oracle import psatd_oracle as O
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__)))
+    from psatd_cases import random_fields
+
+    N, d, p, c, dt, steps = (16, 12, 10), (1.0, 1.0, 1.0), 8, 1.0, 0.4, 3
+    E0, B0, J = random_fields(N, 7, d, p)
+    E, B = O.run_global(E0, B0, J, d, p, c, dt, steps)
+
+    class Inputs:
+        def __init__(self):
+            self.N = N
+
+        def field(self, which, dtype, dev):
+            src = {"E": E0, "J": J}[which]
+            return [torch.from_numpy(src[u].copy()).to(dev, dtype).reshape(-1) for u in range(3)]
+
+    kt = [O.modified_k(N[u], d[u], p) for u in range(3)]
+    final = [torch.from_numpy(F[u].copy()).reshape(-1) for F in (E, B) for u in range(3)]
+    diag = bench.field_diagnostics(final, Inputs(), kt, steps * dt, c, dev="cpu")
+    assert diag["div_B_rel"] < 1e-13
+    assert diag["gauss_rel"] < 1e-13
+    assert diag["energy"] == pytest.approx(0.5 * (np.sum(E * E) + np.sum(B * B)), rel=1e-12)
+    # a longitudinal bump in E_x (a gradient field) breaks Gauss's law only
+    x = np.arange(N[0])
+    bump = np.broadcast_to(np.sin(2 * np.pi * x / N[0]), E[0].shape)
+    final[0] = torch.from_numpy((E[0] + 1e-3 * bump).copy()).reshape(-1)
+    bad = bench.field_diagnostics(final, Inputs(), kt, steps * dt, c, dev="cpu")
+    assert bad["gauss_rel"] > 1e-5
+    assert bad["div_B_rel"] < 1e-13

@@ -1,5 +1,6 @@
 """GPU: the truncation sweep harness (local-FFT vs PSATD-global on the GPU)
-against the same difference computed by the FP64 oracle (Sec. 3.2, Fig. 3)."""
+against the same difference computed by the FP64 oracle (Sec. 3.2, Fig. 3),
+over the guard width and the resolution axis."""
 import numpy as np
 import pytest
 
@@ -20,26 +21,58 @@ def _gpu():
     yield
 
 
+def _oracle_kmod(N, d, p):
+    return [O.modified_k(N[u], d[u], p) for u in range(3)]
+
+
+def _oracle_difference(F, N, nbox, gw, d, p, c, dt, steps):
+    E, B, J = F
+    Eg, Bg = O.run_global(E, B, J, d, p, c, dt, steps)
+    lo, n, g = synth.uniform_decomposition(N, nbox, gw)
+    dec = O.Decomposition(N, lo, n, g)
+    Eb, Bb, _ = O.run_local(O.scatter(E, dec), O.scatter(B, dec), O.scatter(J, dec), dec, d, p, c,
+                            dt, steps)
+    El, Bl = O.gather(Eb, dec), O.gather(Bb, dec)
+    den = float(np.sum(Eg ** 2) + c * c * np.sum(Bg ** 2))
+    return float(np.sqrt((np.sum((El - Eg) ** 2) + c * c * np.sum((Bl - Bg) ** 2)) / den))
+
+
 def test_guard_sweep_matches_oracle_and_falls_with_guards():
     from paper_1707_08500_amd import truncation as T
     N, nbox, p, steps, dt, c = (48, 48, 48), (3, 3, 3), 16, 4, 0.5, 1.0
     d = (1.0, 1.0, 1.0)
-    say("truncation sweep 48^3 3x3x3 p=16 g=4,8,12")
-    fields = T.smooth_fields(N, d)
-    rows = T.sweep(N, nbox, [p], [4, 8, 12], steps, dt=dt, c=c, fields=fields)
-    E, B, J = fields
-    Eg, Bg = O.run_global(E, B, J, d, p, c, dt, steps)
-    den = float(np.sum(Eg ** 2) + np.sum(Bg ** 2))
-    for r in rows:
-        lo, n, g = synth.uniform_decomposition(N, nbox, r["g"])
-        dec = O.Decomposition(N, lo, n, g)
-        Eb, Bb, _ = O.run_local(O.scatter(E, dec), O.scatter(B, dec), O.scatter(J, dec), dec, d, p, c,
-                                dt, steps)
-        El, Bl = O.gather(Eb, dec), O.gather(Bb, dec)
-        ref = float(np.sqrt((np.sum((El - Eg) ** 2) + np.sum((Bl - Bg) ** 2)) / den))
+    say("truncation sweep 48^3 3x3x3 p=16 g=4,8,12, broadband input")
+    # the input's polarisations use the oracle's [k]: no oracle input comes
+    # from the library
+    F = T.smooth_fields(N, _oracle_kmod(N, d, p), d, c)
+    rows = T.sweep(N, nbox, [p], [4, 8, 12], [2, steps], dt=dt, c=c, fields=lambda p_, w: F)
+    last = [r for r in rows if r["steps"] == steps]
+    for r in last:
+        ref = _oracle_difference(F, N, nbox, r["g"], d, p, c, dt, steps)
         say(f"  g={r['g']}: gpu {r['energy']:.6e} oracle {ref:.6e}")
         assert abs(r["energy"] - ref) <= 1e-9
-    e = [r["energy"] for r in rows]
+    e = [r["energy"] for r in last]
     assert e[0] > e[1] > e[2]
     need = T.guards_needed(rows, e[1])
-    assert need[p] == 8
+    assert need[(p, "smooth")] == 8
+
+
+def test_resolution_axis_matches_oracle_and_falls_with_guards():
+    """Laser-like pulses of 24 and 6 cells per wavelength crossing the box
+    boundaries: the GPU's local-vs-global difference equals the oracle's at
+    each (resolution, guard width), and falls with the guard width."""
+    from paper_1707_08500_amd import truncation as T
+    N, nbox, p, steps, dt, c = (48, 48, 48), (3, 3, 3), 16, 4, 0.5, 1.0
+    d = (1.0, 1.0, 1.0)
+    fields = {w: T.resolution_fields(N, w, 4.0, c) for w in (24.0, 6.0)}
+    say("truncation resolution axis 48^3 3x3x3 p=16 g=4,8, 24 and 6 cells per wavelength")
+    rows = T.sweep(N, nbox, [p], [4, 8], [steps], dt=dt, c=c, waves=(24.0, 6.0),
+                   fields=lambda p_, w: fields[w])
+    for w in (24.0, 6.0):
+        mine = {r["g"]: r for r in rows if r["cells_per_wavelength"] == w}
+        for gw, r in mine.items():
+            assert r["kdx"] == pytest.approx(2 * np.pi / w)
+            ref = _oracle_difference(fields[w], N, nbox, gw, d, p, c, dt, steps)
+            say(f"  {w:g} cells/wavelength g={gw}: gpu {r['energy']:.6e} oracle {ref:.6e}")
+            assert abs(r["energy"] - ref) <= 1e-9
+        assert mine[4]["energy"] > mine[8]["energy"]
