@@ -17,7 +17,8 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpsatd.so")
 
 SOURCES = ["psatd_api.hip", "psatd_kernels.hip"]
-HEADERS = ["fft_engine.hpp", "psatd_device.hpp", "psatd_launch.hpp", "plan_host.hpp", "dft_consts.h"]
+HEADERS = ["fft_engine.hpp", "psatd_device.hpp", "psatd_launch.hpp", "plan_host.hpp", "dft_consts.h",
+           "mfma_dft.hpp", "reg_fft.hpp", "zreg.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

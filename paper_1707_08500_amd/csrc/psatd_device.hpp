@@ -138,9 +138,13 @@ struct alignas(2 * sizeof(V) < 16 ? 2 * sizeof(V) : 16) Pair {
 };
 
 // Row-major R x C walk shared by a work-group: element i = tid + k nt, with
-// its (row, col) advanced incrementally (no per-element division); full
-// batches of U run without bounds checks.  get(i, r, c) -> V, put(i, r, c, v).
-template <int U, class V, class Get, class Put>
+// its (row, col) advanced incrementally (no per-element division), in
+// batches of U whose U loads are all issued before the first store; full
+// batches run without bounds checks.  The remainder (fewer than U per
+// thread) runs one element at a time, or with TAILB as one more guarded
+// batch (fewer round trips to memory, more registers live at once).
+// get(i, r, c) -> V, put(i, r, c, v).
+template <int U, class V, bool TAILB = false, class Get, class Put>
 PSATD_HD void copy_grid(int R, int C, int tid, int nt, Get get, Put put) {
   const int total = R * C;
   const FastDiv dC = make_fastdiv((uint32_t)C);
@@ -170,16 +174,31 @@ PSATD_HD void copy_grid(int R, int C, int tid, int nt, Get get, Put put) {
 #pragma unroll
     for (int u = 0; u < U; ++u) put(i + u * nt, rs[u], cs[u], v[u]);
   }
-  for (; i < total; i += nt) {
-    put(i, r, c, get(i, r, c));
-    advance(r, c);
+  if (!TAILB) {
+    for (; i < total; i += nt) {
+      put(i, r, c, get(i, r, c));
+      advance(r, c);
+    }
+  } else if (i < total) {  // the last, partial batch, its loads in flight together
+    V v[U];
+    int rs[U], cs[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      rs[u] = r;
+      cs[u] = c;
+      if (i + u * nt < total) v[u] = get(i + u * nt, r, c);
+      advance(r, c);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i + u * nt < total) put(i + u * nt, rs[u], cs[u], v[u]);
   }
 }
 
 // The same walk over the pairs (e, e+1), e = 2 j, of a row-major R x C grid
 // with R C even (a pair may straddle two rows): get(j, r0, c0, r1, c1) -> V,
 // put(j, r0, c0, r1, c1, v), with (r1, c1) the position of e + 1.
-template <int U, class V, class Get, class Put>
+template <int U, class V, bool TAILB = false, class Get, class Put>
 PSATD_HD void copy_grid_pairs(int R, int C, int tid, int nt, Get get, Put put) {
   const int total = (R * C) >> 1;
   const FastDiv dC = make_fastdiv((uint32_t)C);
@@ -220,15 +239,37 @@ PSATD_HD void copy_grid_pairs(int R, int C, int tid, int nt, Get get, Put put) {
       put(j + u * nt, rs[u], cs[u], r1, c1, v[u]);
     }
   }
-  for (; j < total; j += nt) {
-    int r1, c1;
-    second(r, c, r1, c1);
-    put(j, r, c, r1, c1, get(j, r, c, r1, c1));
-    advance(r, c);
+  if (!TAILB) {
+    for (; j < total; j += nt) {
+      int r1, c1;
+      second(r, c, r1, c1);
+      put(j, r, c, r1, c1, get(j, r, c, r1, c1));
+      advance(r, c);
+    }
+  } else if (j < total) {  // the last, partial batch
+    V v[U];
+    int rs[U], cs[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      rs[u] = r;
+      cs[u] = c;
+      int r1, c1;
+      second(r, c, r1, c1);
+      if (j + u * nt < total) v[u] = get(j + u * nt, r, c, r1, c1);
+      advance(r, c);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (j + u * nt < total) {
+        int r1, c1;
+        second(rs[u], cs[u], r1, c1);
+        put(j + u * nt, rs[u], cs[u], r1, c1, v[u]);
+      }
   }
 }
 
-// The same walk over an A x B x C box (C fastest): get(i, a, b, c), put(i, a, b, c, v).
+// The same walk over an A x B x C box (C fastest), the remainder always as a
+// guarded batch: get(i, a, b, c), put(i, a, b, c, v).
 template <int U, class V, class Get, class Put>
 PSATD_HD void copy_grid3(int A, int B, int C, int tid, int nt, Get get, Put put) {
   const int total = A * B * C;
@@ -271,9 +312,20 @@ PSATD_HD void copy_grid3(int A, int B, int C, int tid, int nt, Get get, Put put)
 #pragma unroll
     for (int u = 0; u < U; ++u) put(i + u * nt, as[u], bs[u], cs[u], v[u]);
   }
-  for (; i < total; i += nt) {
-    put(i, a, b, c, get(i, a, b, c));
-    advance(a, b, c);
+  if (i < total) {  // the last, partial batch
+    V v[U];
+    int as[U], bs[U], cs[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      as[u] = a;
+      bs[u] = b;
+      cs[u] = c;
+      if (i + u * nt < total) v[u] = get(i + u * nt, a, b, c);
+      advance(a, b, c);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i + u * nt < total) put(i + u * nt, as[u], bs[u], cs[u], v[u]);
   }
 }
 
@@ -647,7 +699,9 @@ PSATD_HD void body_z_update(const UpdArgs<T>& a, int item, int tid, int nt, cx<T
   const bool pairs = (PB % 2) == 0 && np == PB &&
                      (((int64_t)nq | slab | (int64_t)(9 * (bx.soff - a.sbias) + q0)) & 1) == 0;
   if (pairs) {
-    copy_grid3<4, Pair<cx<T>>>(9, Pz, PB / 2, tid, nt,
+    // up to 8 loads in flight per thread (a 96-plane FP32 tile of 8 pencils is
+    // 6.75 pairs per thread of 512: one batch)
+    copy_grid3<8, Pair<cx<T>>>(9, Pz, PB / 2, tid, nt,
         [&](int, int f, int z, int p2) {
           return *reinterpret_cast<const Pair<cx<T>>*>(src + f * slab + (int64_t)z * nq + 2 * p2);
         },
@@ -834,13 +888,13 @@ PSATD_HD void body_inv_xy(const InvArgs<T>& a, int item, int tid, int nt, cx<T>*
   // FP32: two spectrum entries per access (measured slower in FP64)
   if (sizeof(T) == 4 && ((Py * H) & 1) == 0 && (reinterpret_cast<uintptr_t>(src) % sizeof(Pair<cx<T>>)) == 0) {
     const Pair<cx<T>>* src2 = reinterpret_cast<const Pair<cx<T>>*>(src);
-    copy_grid_pairs<4, Pair<cx<T>>>(Py, H, tid, nt, [&](int j, int, int, int, int) { return src2[j]; },
+    copy_grid_pairs<4, Pair<cx<T>>, true>(Py, H, tid, nt, [&](int j, int, int, int, int) { return src2[j]; },
         [&](int, int r0, int c0, int r1, int c1, Pair<cx<T>> v) {
           lds[posy[r0] * ld + c0] = v.a;
           lds[posy[r1] * ld + c1] = v.b;
         });
   } else {
-    copy_grid<8, cx<T>>(Py, H, tid, nt, [&](int i, int, int) { return src[i]; },
+    copy_grid<8, cx<T>, true>(Py, H, tid, nt, [&](int i, int, int) { return src[i]; },
                         [&](int, int ky, int kx, cx<T> v) { lds[posy[ky] * ld + kx] = v; });
   }
   bar();

@@ -48,6 +48,10 @@ class PsatdError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1707_08500_amd.build`")
+    # torch first: its HIP runtime is then the one the library binds to, so
+    # the process holds a single runtime (loaded the other way round, the
+    # library's own runtime came up without a device next to torch's)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
