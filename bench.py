@@ -270,12 +270,14 @@ def traffic_path(workload):
 
 
 def _pmc_rows(path, counter):
-    """Per-dispatch values of one counter from a rocprofv3 counter_collection.csv."""
+    """Per-dispatch values of one counter from a rocprofv3 counter_collection.csv,
+    in dispatch order."""
     rows = []
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] == counter:
-            rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
-    return rows
+            rows.append((int(r.get("Dispatch_Id") or 0), r["Kernel_Name"], float(r["Counter_Value"])))
+    rows.sort(key=lambda t: t[0])
+    return [(name, v) for _, name, v in rows]
 
 
 def summarize_pmc(fetch_csv, write_csv, workload, command):
@@ -286,9 +288,11 @@ def summarize_pmc(fetch_csv, write_csv, workload, command):
     factors = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = _pmc_rows(path, counter)
-        # the calibration dispatches are the only ones outside the library that
-        # move more than 256 MiB: the 1 GiB fill (writes) and the 1 GiB copies
-        copies = [v for name, v in rows if "psatd" not in name and v > 0.25 * COPY_BYTES / 1024]
+        # the calibration dispatches come before the library's first one and
+        # are the only ones there that move more than 256 MiB: the 1 GiB fill
+        # (writes) and the 1 GiB copies
+        first = next((i for i, (name, _) in enumerate(rows) if "psatd" in name), len(rows))
+        copies = [v for name, v in rows[:first] if v > 0.25 * COPY_BYTES / 1024]
         if not copies:
             raise SystemExit(f"no 1 GiB calibration dispatch among the {counter} dispatches")
         factors[counter] = (COPY_BYTES / 1024) / (sum(copies) / len(copies))
@@ -380,6 +384,38 @@ def summarize_mix(csvs, workload, command):
         for k in sorted(mean):
             if any(c in mean[k] for c in rest):
                 lines.append(f"{k} | " + " | ".join(f"{mean[k].get(c, 0.0):.4g}" for c in rest))
+    return "\n".join(lines) + "\n"
+
+
+def summarize_mfma(counter_csv, agent_csv, workload, command):
+    """Matrix-core use per dispatch of every psatd kernel from one rocprofv3
+    --pmc pass (SQ_INSTS_VALU_MFMA_MOPS_BF16, SQ_VALU_MFMA_BUSY_CYCLES,
+    GRBM_GUI_ACTIVE, SQ_INSTS_MFMA, SQ_INSTS_VALU): BF16 flops = MOPS x 512,
+    their rate over the dispatch's profiled duration against the 2.5 PFLOP/s
+    dense BF16 peak, and MFMA busy = busy cycles / (active cycles per XCD x
+    SIMDs), with the XCD and SIMD counts from the profiler's agent record."""
+    gpu = [r for r in csv.DictReader(open(agent_csv)) if r.get("Name", "").startswith("gfx")][0]
+    nxcc, nsimd = int(gpu["Num_Xcc"]), int(gpu["Simd_Count"])
+    per, dur = {}, {}
+    for r in csv.DictReader(open(counter_csv)):
+        if "psatd" not in r["Kernel_Name"]:
+            continue
+        k = r["Kernel_Name"].split("(")[0].replace("void ", "").strip()
+        per.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        dur.setdefault(k, {})[r["Dispatch_Id"]] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    lines = [f"# matrix-core (MFMA) use per dispatch, workload {workload}",
+             f"# command: {command}",
+             f"source_digest: {source_digest()}",
+             f"# {gpu['Name']}: {nxcc} XCDs, {nsimd} SIMDs; GRBM_GUI_ACTIVE is summed over the XCDs",
+             "# kernel | profiled us | MFMA instr | VALU instr | BF16 GFLOP | BF16 TFLOP/s | of 2500 | MFMA busy"]
+    for k in sorted(per):
+        m = {c: sum(v) / len(v) for c, v in per[k].items()}
+        t = sum(dur[k].values()) / len(dur[k]) * 1e-9
+        flop = m.get("SQ_INSTS_VALU_MFMA_MOPS_BF16", 0.0) * 512
+        active = m.get("GRBM_GUI_ACTIVE", 0.0) / nxcc
+        busy = m.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (active * nsimd) if active else 0.0
+        lines.append(f"{k} | {t * 1e6:.1f} | {m.get('SQ_INSTS_MFMA', 0.0):.4g} | {m.get('SQ_INSTS_VALU', 0.0):.4g} | "
+                     f"{flop / 1e9:.1f} | {flop / t / 1e12:.1f} | {flop / t / 2.5e15:.3f} | {busy:.3f}")
     return "\n".join(lines) + "\n"
 
 
@@ -629,6 +665,8 @@ def main():
                     help="time launch-shape candidates first (the defaults are the measured best)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM-traffic summary from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--summarize-mfma", nargs=2, metavar=("COUNTER_CSV", "AGENT_CSV"),
+                    help="print the matrix-core summary of a rocprofv3 --pmc run and exit")
     ap.add_argument("--pmc-command", default="", help="the profiled command, recorded in the summary")
     ap.add_argument("--summarize-ktrace", nargs=2, metavar=("KERNEL_STATS_CSV", "BENCH_LOG"),
                     help="print the kernel-statistics summary of a rocprofv3 --stats run and exit")
@@ -653,6 +691,10 @@ def main():
             if line.startswith("{"):
                 bench_line = line
         print(summarize_ktrace(args.summarize_ktrace[0], bench_line, args.workload, args.pmc_command),
+              end="")
+        return
+    if args.summarize_mfma:
+        print(summarize_mfma(args.summarize_mfma[0], args.summarize_mfma[1], args.workload, args.pmc_command),
               end="")
         return
     if args.summarize_mix:
