@@ -102,7 +102,11 @@ typedef enum {
                                  the workspace then holds one batch's half spectra */
   PSATD_TUNE_MAX_RADIX = 7,   /* largest radix of the FFT schedules: 16, or 8 (fewer registers, more
                                  stages); radix 11 is always allowed */
-  PSATD_TUNE_XY_THREADS = 8,  /* threads per work-group of the x/y passes: 256, 512 or 1024 */
+  PSATD_TUNE_XY_THREADS = 8,  /* threads per work-group of the x/y passes: 256, 512 or 1024 for every
+                                 subdomain; 0 (default for unbatched plans whose subdomains differ in how
+                                 many padded planes fit a compute unit's LDS): one launch per such class,
+                                 each with the fewest threads that keep 16 waves per compute unit and the
+                                 LDS of its own largest plane */
   PSATD_TUNE_Z_THREADS = 9,   /* threads per work-group of the z-update: 512 or 1024 */
   PSATD_TUNE_SPLIT_XY = 10,   /* 1: x rows and y columns in separate passes through the workspace
                                  (automatic when a padded plane exceeds the LDS; needs no batching) */

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "psatd.h"
@@ -57,6 +58,9 @@ struct HostTables {
   int ntxy = 512;     // threads per work-group of the x/y passes
   int ntu = 512;      // threads per work-group of the z-update (1024 for FP32 by default)
   bool zreg = false;  // the register z pass applies (FP32 VALU form, every padded z length scheduled)
+  std::vector<int32_t> boxlds;     // dynamic LDS bytes of one x/y plane of each box
+  std::vector<XyClass> xyc;       // x/y launch classes (empty: one launch for every box)
+  std::vector<int32_t> itemsXYC;  // their work lists
   std::vector<ZGroup> zgroups;    // one per distinct padded z length
   std::vector<int32_t> itemsZR;   // their work lists, nsub + 1 prefix entries each
 };
@@ -386,6 +390,58 @@ inline void build_push(HostTables& h) {
     for (int32_t i = h.itemsG[b]; i < h.itemsG[b + 1]; ++i) h.pieceOf[i] = (int32_t)b;
 }
 
+// Threads per x/y work-group for planes of `lds` bytes: the fewest (256, 512
+// or 1024) that still keep 16 waves on a compute unit, given how many planes
+// fit its LDS.
+inline int xy_threads_for(int lds) {
+  const int per_cu = lds > 0 ? std::max(1, kMaxDynLds / lds) : 1;
+  for (int nt : {256, 512})
+    if (per_cu * nt / 64 >= 16) return nt;
+  return 1024;
+}
+
+// Launch classes of the x/y passes: boxes grouped by their group size, each
+// class launched with its own LDS (the largest plane among its boxes), so
+// small boxes are not held to one group per compute unit by the largest box
+// of an uneven decomposition.  None when every box has the same group size or
+// the planes take the split passes.
+inline void build_xy_classes(HostTables& h) {
+  h.xyc.clear();
+  h.itemsXYC.clear();
+  if (h.split) return;
+  const int sizes[kMaxXyClasses] = {256, 512, 1024};
+  std::vector<int> cls(h.nsub);
+  int used = 0;
+  for (int s = 0; s < h.nsub; ++s) {
+    const int nt = xy_threads_for(h.boxlds[s]);
+    cls[s] = nt == 256 ? 0 : (nt == 512 ? 1 : 2);
+    used |= 1 << cls[s];
+  }
+  if (used == 1 || used == 2 || used == 4) return;  // one class: one launch
+  auto prefix = [&](int c, auto count) {
+    const int32_t off = (int32_t)h.itemsXYC.size();
+    int32_t acc = 0;
+    h.itemsXYC.push_back(0);
+    for (int s = 0; s < h.nsub; ++s) {
+      if (cls[s] == c) acc += (int32_t)count(h.box[s]);
+      h.itemsXYC.push_back(acc);
+    }
+    return std::make_pair(off, acc);
+  };
+  for (int c = 0; c < kMaxXyClasses; ++c) {
+    if (!(used & (1 << c))) continue;
+    XyClass k{};
+    k.nt = sizes[c];
+    for (int s = 0; s < h.nsub; ++s)
+      if (cls[s] == c) k.lds = std::max(k.lds, h.boxlds[s]);
+    std::tie(k.F, k.nF) = prefix(c, [](const BoxD& b) { return (int64_t)b.P[2] * 9; });
+    std::tie(k.P, k.nP) = prefix(c, [](const BoxD& b) { return (int64_t)b.P[2]; });
+    std::tie(k.I, k.nI) = prefix(c, [](const BoxD& b) { return (int64_t)b.n[2] * 6; });
+    std::tie(k.N, k.nN) = prefix(c, [](const BoxD& b) { return (int64_t)b.n[2]; });
+    h.xyc.push_back(k);
+  }
+}
+
 // Pencils per work-group of the register z pass for padded z length N (0: no schedule).
 inline int zreg_pencils_of(int N) {
 #define PSATD_ZREG_P(N_, L_, W_, MINW_) \
@@ -546,8 +602,8 @@ inline psatd_status build_host(HostTables& h, std::string& err, const int64_t gr
     foff += (int64_t)b.P[0] * b.P[1] * b.P[2];
     soff += (int64_t)b.H * b.P[1] * b.P[2];
     // plane + twiddles of the x plan, the y plan and W_Px + position tables
-    h.ldsF = std::max<int>(h.ldsF, (b.P[1] * b.ld + b.P[0] / 2 + b.P[1] + b.P[0]) * csz +
-                                       (b.P[0] / 2 + b.P[1]) * 4);
+    h.boxlds.push_back((b.P[1] * b.ld + b.P[0] / 2 + b.P[1] + b.P[0]) * csz + (b.P[0] / 2 + b.P[1]) * 4);
+    h.ldsF = std::max<int>(h.ldsF, h.boxlds.back());
     h.ldsI = h.ldsF;
     maxPz = std::max(maxPz, b.P[2]);
   }
@@ -615,15 +671,8 @@ inline psatd_status build_host(HostTables& h, std::string& err, const int64_t gr
   // 127 KB plane x 1024 threads); 512-thread z tiles of 8 pencils; FP64
   // stages of radix <= 8
   h.ntu = 512;
-  {
-    const int per_cu = h.ldsF > 0 ? std::max(1, kMaxDynLds / h.ldsF) : 1;
-    h.ntxy = 1024;
-    for (int nt : {256, 512})
-      if (per_cu * nt / 64 >= 16) {
-        h.ntxy = nt;
-        break;
-      }
-  }
+  h.ntxy = xy_threads_for(h.ldsF);
+  build_xy_classes(h);
   if (f64 && !set_max_radix(h, 8)) return bad(PSATD_E_UNSUPPORTED, "no radix-8 schedule");
   return PSATD_OK;
 }

@@ -328,6 +328,7 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   const size_t o_iZR = reserve(std::max<size_t>(h.itemsZR.size(), 1) * 4);
   const size_t o_pull = reserve(std::max<size_t>(h.pullp.size(), 1) * sizeof(PullPiece));
   const size_t o_poff = reserve(h.pull_off.size() * 4);
+  const size_t o_xyc = reserve(std::max<size_t>(h.itemsXYC.size(), 1) * 4);
   std::vector<unsigned char> hb(total, 0);
   auto put = [&](size_t off, const void* src, size_t bytes) {
     if (bytes) std::memcpy(hb.data() + off, src, bytes);
@@ -357,6 +358,7 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   put(o_iZR, h.itemsZR.data(), h.itemsZR.size() * 4);
   put(o_pull, h.pullp.data(), h.pullp.size() * sizeof(PullPiece));
   put(o_poff, h.pull_off.data(), h.pull_off.size() * 4);
+  put(o_xyc, h.itemsXYC.data(), h.itemsXYC.size() * 4);
   if ((e = hipMalloc(&p->blob, total)) != hipSuccess) return hipfail(e, "hipMalloc(tables)");
   if ((e = hipMemcpy(p->blob, hb.data(), total, hipMemcpyHostToDevice)) != hipSuccess)
     return hipfail(e, "hipMemcpy(tables)");
@@ -365,7 +367,8 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
     return hipfail(e, "hipMemcpy(work list)");
   p->tune[PSATD_TUNE_Z_PENCILS] = h.PB;
   p->tune[PSATD_TUNE_MAX_RADIX] = h.maxr;
-  p->tune[PSATD_TUNE_XY_THREADS] = h.ntxy;
+  // boxes of several plane sizes: one x/y launch per class (xy_threads 0)
+  p->tune[PSATD_TUNE_XY_THREADS] = h.xyc.size() > 1 ? 0 : h.ntxy;
   p->tune[PSATD_TUNE_Z_THREADS] = h.ntu;
   p->tune[PSATD_TUNE_SPLIT_XY] = h.split ? 1 : 0;
   unsigned char* B = reinterpret_cast<unsigned char*>(p->blob);
@@ -435,7 +438,10 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   d.PB = h.PB;
   d.ldsH = heat_lds(h);
   d.ntu = h.ntu;
-  d.ntxy = h.ntxy;
+  d.ntxy = p->tune[PSATD_TUNE_XY_THREADS];
+  d.nxyc = (int32_t)h.xyc.size();
+  for (int i = 0; i < d.nxyc; ++i) d.xyc[i] = h.xyc[i];
+  d.itemsXYC = reinterpret_cast<const int32_t*>(B + o_xyc);
   d.maxr = h.maxr;
   d.xcd = 1;
   d.slab = h.batch_slab;
@@ -701,6 +707,10 @@ psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
         p->tune[PSATD_TUNE_FUSE_EB] = 0;
         d.pull = 0;  // and its owners' old interiors
         p->tune[PSATD_TUNE_PULL_EB] = 0;
+        if (d.ntxy == 0) {  // batches launch every box of a batch with one group size
+          d.ntxy = p->h.ntxy;
+          p->tune[PSATD_TUNE_XY_THREADS] = p->h.ntxy;
+        }
       }
       break;
     }
@@ -754,9 +764,12 @@ psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
       break;
     }
     case PSATD_TUNE_XY_THREADS:
-      if (value != 256 && value != 512 && value != 1024)
-        return fail(p, PSATD_E_INVALID, "x/y threads must be 256, 512 or 1024");
-      p->h.ntxy = value;
+      if (value != 0 && value != 256 && value != 512 && value != 1024)
+        return fail(p, PSATD_E_INVALID, "x/y threads must be 0 (per launch class), 256, 512 or 1024");
+      if (value == 0 && (p->h.xyc.size() < 2 || p->h.batches.size() > 1))
+        return fail(p, PSATD_E_INVALID,
+                    "per-class x/y launches need an unbatched plan whose boxes have several plane sizes");
+      if (value) p->h.ntxy = value;
       d.ntxy = value;
       break;
     case PSATD_TUNE_Z_THREADS:
@@ -849,9 +862,11 @@ psatd_status psatd_autotune(psatd_plan_t p, void* const E[3], void* const B[3], 
     int cxy = 256, cpb = p->h.PB, czt = 512, cx = 1;
     for (int xcd : {1, 0}) {
       if ((r = psatd_set_tuning(p, PSATD_TUNE_XCD_REMAP, xcd)) != PSATD_OK) return r;
-      for (int xy : {256, 512, 1024}) {
+      for (int xy : {0, 256, 512, 1024}) {
         // the split x/y passes run fixed 256-thread groups: one x/y shape to time
         if (p->h.split && xy != 256) continue;
+        // 0: one launch per class of plane size, for uneven boxes of an unbatched plan
+        if (xy == 0 && (p->h.xyc.size() < 2 || p->h.batches.size() > 1)) continue;
         if ((r = psatd_set_tuning(p, PSATD_TUNE_XY_THREADS, xy)) != PSATD_OK) return r;
         for (int pb : {16, 8, 4}) {
           if (psatd_set_tuning(p, PSATD_TUNE_Z_PENCILS, pb) != PSATD_OK) continue;

@@ -83,6 +83,18 @@ struct ZGroup {
 };
 constexpr int kMaxZGroups = 8;
 
+// A launch class of the x/y passes: the boxes whose padded planes fit the
+// same number of times into a compute unit's LDS, run with their own group
+// size and dynamic LDS.  Its work lists are prefixes over all boxes (zero for
+// the boxes of other classes) at the given offsets of one table: planes of the
+// 9 fields (F), of one field (P), interior planes of the 6 outputs (I) and of
+// one output (N), with their totals.
+struct XyClass {
+  int32_t nt, lds;
+  int32_t F, nF, P, nP, I, nI, N, nN;
+};
+constexpr int kMaxXyClasses = 3;
+
 // Pencils per work-group of the register z pass (9 fields share its lanes).
 constexpr int zreg_pencils(int L, int W) { return (64 * W / L) / 9; }
 

@@ -300,10 +300,35 @@ hipError_t launch_sum(const DevPlan& p, void* const* J, hipStream_t st) {
   } while (0)
 
 template <typename T, int NT, int MAXR, int SPL>
-static hipError_t fwd_go(const DevPlan& p, const Batch& b, const FwdArgs<T>& a, int g, hipStream_t st) {
-  hipLaunchKernelGGL((k_fwd_xy<T, NT, MAXR, SPL>), dim3(g), dim3(NT), p.ldsF, st, a, b.F0, b.nF, p.xcd);
+static hipError_t fwd_go(const DevPlan& p, const FwdArgs<T>& a, int g, int lds, int item0, int n,
+                         hipStream_t st) {
+  hipLaunchKernelGGL((k_fwd_xy<T, NT, MAXR, SPL>), dim3(g), dim3(NT), lds, st, a, item0, n, p.xcd);
   return hipGetLastError();
 }
+
+// One x/y launch of n items from item0 with nt threads per group.
+template <typename T, class Go>
+static hipError_t xy_shape(const DevPlan& p, int nt, Go go) {
+  return with_spl<T>(p.spl, [&](auto sc) -> hipError_t {
+    constexpr int SPL = decltype(sc)::value;
+    if (nt == 1024)
+      PSATD_MAXR_SWITCH(SPL, return (go.template run<1024, 8, SPL>()), return (go.template run<1024, 16, SPL>()));
+    if (nt == 512)
+      PSATD_MAXR_SWITCH(SPL, return (go.template run<512, 8, SPL>()), return (go.template run<512, 16, SPL>()));
+    PSATD_MAXR_SWITCH(SPL, return (go.template run<256, 8, SPL>()), return (go.template run<256, 16, SPL>()));
+    return hipSuccess;
+  });
+}
+
+template <typename T>
+struct FwdGo {
+  const DevPlan& p;
+  const FwdArgs<T>& a;
+  int g, lds, item0, n;
+  hipStream_t st;
+  template <int NT, int MAXR, int SPL>
+  hipError_t run() const { return fwd_go<T, NT, MAXR, SPL>(p, a, g, lds, item0, n, st); }
+};
 
 template <typename T>
 static hipError_t fwd_t(const DevPlan& p, const Batch& b, void* const* in9, void* spec, hipStream_t st,
@@ -318,20 +343,21 @@ static hipError_t fwd_t(const DevPlan& p, const Batch& b, void* const* in9, void
   for (int f = 0; f < 9; ++f) a.in[f] = (f < a.nfield) ? reinterpret_cast<const T*>(in9[f]) : nullptr;
   a.spec = reinterpret_cast<cx<T>*>(spec);
   a.sbias = b.sbias;
+  if (p.ntxy == 0) {  // one launch per class of plane size (unbatched plans only)
+    for (int c = 0; c < p.nxyc; ++c) {
+      const XyClass& k = p.xyc[c];
+      a.items = p.itemsXYC + (scalar ? k.P : k.F);
+      const int n = scalar ? k.nP : k.nF;
+      const int g = grid_for(n, p.grid_cap[kPhaseFwd]);
+      if (!g) continue;
+      const hipError_t e = xy_shape<T>(p, k.nt, FwdGo<T>{p, a, g, k.lds, 0, n, st});
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   const int g = grid_for(b.nF, p.grid_cap[kPhaseFwd]);
   if (!g) return hipSuccess;
-  return with_spl<T>(p.spl, [&](auto sc) -> hipError_t {
-    constexpr int SPL = decltype(sc)::value;
-    if (p.ntxy == 1024)
-      PSATD_MAXR_SWITCH(SPL, return (fwd_go<T, 1024, 8, SPL>(p, b, a, g, st)),
-                        return (fwd_go<T, 1024, 16, SPL>(p, b, a, g, st)));
-    if (p.ntxy == 512)
-      PSATD_MAXR_SWITCH(SPL, return (fwd_go<T, 512, 8, SPL>(p, b, a, g, st)),
-                        return (fwd_go<T, 512, 16, SPL>(p, b, a, g, st)));
-    PSATD_MAXR_SWITCH(SPL, return (fwd_go<T, 256, 8, SPL>(p, b, a, g, st)),
-                      return (fwd_go<T, 256, 16, SPL>(p, b, a, g, st)));
-    return hipSuccess;
-  });
+  return xy_shape<T>(p, p.ntxy, FwdGo<T>{p, a, g, p.ldsF, b.F0, b.nF, st});
 }
 
 hipError_t launch_fwd(const DevPlan& p, const Batch& b, void* const* in9, void* spec, hipStream_t st,
@@ -416,15 +442,26 @@ hipError_t launch_upd_reg(const DevPlan& p, void* spec, hipStream_t st) {
 }
 
 template <typename T, int NT, int MAXR, int SPL>
-static hipError_t inv_go(const DevPlan& p, const Batch& b, const InvArgs<T>& a, int g, hipStream_t st) {
+static hipError_t inv_go(const DevPlan& p, const InvArgs<T>& a, int g, int lds, int item0, int n,
+                         hipStream_t st) {
   if (a.push_off)
-    hipLaunchKernelGGL((k_inv_xy<T, IncOf<T>::value, NT, MAXR, SPL, true>), dim3(g), dim3(NT), p.ldsI, st, a,
-                       b.I0, b.nI, p.xcd);
+    hipLaunchKernelGGL((k_inv_xy<T, IncOf<T>::value, NT, MAXR, SPL, true>), dim3(g), dim3(NT), lds, st, a,
+                       item0, n, p.xcd);
   else
-    hipLaunchKernelGGL((k_inv_xy<T, IncOf<T>::value, NT, MAXR, SPL, false>), dim3(g), dim3(NT), p.ldsI, st, a,
-                       b.I0, b.nI, p.xcd);
+    hipLaunchKernelGGL((k_inv_xy<T, IncOf<T>::value, NT, MAXR, SPL, false>), dim3(g), dim3(NT), lds, st, a,
+                       item0, n, p.xcd);
   return hipGetLastError();
 }
+
+template <typename T>
+struct InvGo {
+  const DevPlan& p;
+  const InvArgs<T>& a;
+  int g, lds, item0, n;
+  hipStream_t st;
+  template <int NT, int MAXR, int SPL>
+  hipError_t run() const { return inv_go<T, NT, MAXR, SPL>(p, a, g, lds, item0, n, st); }
+};
 
 template <typename T>
 static hipError_t inv_t(const DevPlan& p, const Batch& b, const void* spec, void* const* out6, hipStream_t st,
@@ -437,20 +474,21 @@ static hipError_t inv_t(const DevPlan& p, const Batch& b, const void* spec, void
   for (int f = 0; f < 6; ++f) a.out[f] = (f == 0 || !scalar) ? reinterpret_cast<T*>(out6[f]) : nullptr;
   a.push = (p.fuse && !scalar) ? p.push : nullptr;
   a.push_off = (p.fuse && !scalar) ? p.push_off : nullptr;
+  if (p.ntxy == 0) {  // one launch per class of plane size (unbatched plans only)
+    for (int c = 0; c < p.nxyc; ++c) {
+      const XyClass& k = p.xyc[c];
+      a.items = p.itemsXYC + (scalar ? k.N : k.I);
+      const int n = scalar ? k.nN : k.nI;
+      const int g = grid_for(n, p.grid_cap[kPhaseInv]);
+      if (!g) continue;
+      const hipError_t e = xy_shape<T>(p, k.nt, InvGo<T>{p, a, g, k.lds, 0, n, st});
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   const int g = grid_for(b.nI, p.grid_cap[kPhaseInv]);
   if (!g) return hipSuccess;
-  return with_spl<T>(p.spl, [&](auto sc) -> hipError_t {
-    constexpr int SPL = decltype(sc)::value;
-    if (p.ntxy == 1024)
-      PSATD_MAXR_SWITCH(SPL, return (inv_go<T, 1024, 8, SPL>(p, b, a, g, st)),
-                        return (inv_go<T, 1024, 16, SPL>(p, b, a, g, st)));
-    if (p.ntxy == 512)
-      PSATD_MAXR_SWITCH(SPL, return (inv_go<T, 512, 8, SPL>(p, b, a, g, st)),
-                        return (inv_go<T, 512, 16, SPL>(p, b, a, g, st)));
-    PSATD_MAXR_SWITCH(SPL, return (inv_go<T, 256, 8, SPL>(p, b, a, g, st)),
-                      return (inv_go<T, 256, 16, SPL>(p, b, a, g, st)));
-    return hipSuccess;
-  });
+  return xy_shape<T>(p, p.ntxy, InvGo<T>{p, a, g, p.ldsI, b.I0, b.nI, st});
 }
 
 hipError_t launch_inv(const DevPlan& p, const Batch& b, const void* spec, void* const* out6, hipStream_t st,

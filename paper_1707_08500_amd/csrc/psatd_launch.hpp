@@ -44,7 +44,10 @@ struct DevPlan {
   int32_t ldsH;              // heat z pass: one staged field
   int32_t PB;                // pencils per z-update work-group
   int32_t ntu;               // threads per z-update work-group (512 or 1024)
-  int32_t ntxy;              // threads per x/y work-group (256 or 512)
+  int32_t ntxy;              // threads per x/y work-group (256, 512 or 1024; 0: per launch class)
+  int32_t nxyc;              // x/y launch classes (used when ntxy == 0)
+  XyClass xyc[kMaxXyClasses];
+  const int32_t* itemsXYC;
   int32_t maxr;              // largest codelet of the FFT schedules (8 or 16)
   int32_t xcd;               // 1: consecutive items on the same XCD (L2 sharing)
   int64_t slab;              // complex elements of one spectral field slab

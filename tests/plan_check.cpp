@@ -165,8 +165,37 @@ bool check_tables(const Dec& d, const HostTables& h, bool pieces = true) {
   for (int s = 0; s < nsub; ++s)
     CHECK(h.itemsU[s + 1] - h.itemsU[s] == (h.box[s].P[1] * h.box[s].H + h.PB - 1) / h.PB,
           "%s: z work list of box %d", d.name.c_str(), s);
+  // x/y launch classes: every box in exactly one, with its whole work, within the class's LDS
+  if (!h.xyc.empty()) {
+    CHECK(h.xyc.size() >= 2 && h.xyc.size() <= (size_t)kMaxXyClasses, "%s: class count", d.name.c_str());
+    for (int s = 0; s < nsub; ++s) {
+      int in = 0;
+      for (const XyClass& k : h.xyc) {
+        const int32_t* F = h.itemsXYC.data() + k.F;
+        const int32_t* I = h.itemsXYC.data() + k.I;
+        const int cf = F[s + 1] - F[s], ci = I[s + 1] - I[s];
+        if (!cf && !ci) continue;
+        ++in;
+        CHECK(cf == 9 * h.box[s].P[2] && ci == 6 * h.box[s].n[2], "%s: class work of box %d", d.name.c_str(), s);
+        CHECK(h.boxlds[s] <= k.lds && k.lds <= kMaxDynLds, "%s: class LDS of box %d", d.name.c_str(), s);
+        CHECK(k.nt == xy_threads_for(h.boxlds[s]), "%s: class threads of box %d", d.name.c_str(), s);
+      }
+      CHECK(in == 1, "%s: box %d in %d classes", d.name.c_str(), s, in);
+    }
+    int64_t tf = 0, ti = 0;
+    for (const XyClass& k : h.xyc) {
+      tf += k.nF;
+      ti += k.nI;
+      CHECK(h.itemsXYC[k.F + nsub] == k.nF && h.itemsXYC[k.P + nsub] == k.nP && h.itemsXYC[k.I + nsub] == k.nI &&
+                h.itemsXYC[k.N + nsub] == k.nN,
+            "%s: class totals", d.name.c_str());
+    }
+    CHECK(tf == h.itemsF.back() && ti == h.itemsI.back(), "%s: class work lists add up", d.name.c_str());
+  }
   return true;
 }
+
+int g_classes = 0;  // built plans with several x/y launch classes
 
 int run_case(const Dec& d, int prec, int jmode, int p, bool expect_ok, int& built) {
   HostTables h;
@@ -191,6 +220,7 @@ int run_case(const Dec& d, int prec, int jmode, int p, bool expect_ok, int& buil
     return 0;
   }
   ++built;
+  if (!h.xyc.empty()) ++g_classes;
   if (!check_tables(d, h)) return 0;
   // the launch-shape knobs that rebuild host tables
   const int maxPz = max_padded_z(h);
@@ -227,6 +257,12 @@ int main() {
     const int64_t N[3] = {144, 144, 96};
     std::vector<int64_t> cuts[3] = {{0, 48, 112, 144}, {0, 64, 144}, {0, 48, 96}};
     ok.push_back(tiled("uneven, mixed guards", N, cuts, {8, 16, 8, 16, 8, 16, 16, 8, 16}));
+  }
+  {
+    // planes of very different sizes: several x/y launch classes
+    const int64_t N[3] = {192, 64, 48};
+    std::vector<int64_t> cuts[3] = {{0, 32, 192}, {0, 64}, {0, 16, 48}};
+    ok.push_back(tiled("x/y launch classes", N, cuts, {8, 8, 8, 8, 8, 8}));
   }
   {
     const int64_t N[3] = {20, 21, 15};
@@ -302,11 +338,11 @@ int main() {
       ++g_fail;
     }
   }
-  if (g_fail || built < 30 || passed != built) {
+  if (g_fail || built < 30 || passed != built || g_classes == 0) {
     std::fprintf(stderr, "plan_check: FAILED (%d failures, %d built, %d passed)\n", g_fail, built, passed);
     return 1;
   }
-  std::printf("plan_check: ok (%d decompositions x forms built and checked, %zu invalid rejected)\n", built,
-              bad.size());
+  std::printf("plan_check: ok (%d decompositions x forms built and checked, %d with x/y launch classes, "
+              "%zu invalid rejected)\n", built, g_classes, bad.size());
   return 0;
 }

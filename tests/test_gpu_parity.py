@@ -703,3 +703,43 @@ def test_pulled_eb_exchange_is_the_copy_pass(precision, shape):
         case.plan.close()
     for a, b in zip(*out):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_xy_launch_classes(precision, tol):
+    """Subdomains whose padded planes fit a compute unit's LDS a different
+    number of times run the x/y passes as one launch per class (the default,
+    xy_threads 0): the step matches the oracle (Sec. 3.2, Fig. 3) and is
+    byte-identical to one launch of every box with 256 or 1024 threads; the
+    knob rejects 0 once the plan is batched."""
+    import torch
+    from paper_1707_08500_amd import psatd
+    say(f"x/y launch classes, {precision}")
+    N = (192, 64, 48)
+    xc, yc, zc = [0, 32, 192], [0, 64], [0, 16, 48]
+    lo, n = [], []
+    for k in range(2):
+        for i in range(2):
+            lo.append([xc[i], 0, zc[k]])
+            n.append([xc[i + 1] - xc[i], 64, zc[k + 1] - zc[k]])
+    g = [[8, 8, 8]] * 4
+    E, B, J = random_fields(N, 31, p=16)
+    if precision == "f32":
+        E, B, J = (x.astype(np.float32).astype(np.float64) for x in (E, B, J))
+    case, eE, eB, _ = run_both(N, lo, n, g, 16, 0.5, 1.0, precision, "replicated", (E, B, J), 3)
+    assert case.plan.tuning()["xy_threads"] == 0
+    check(case, eE, eB, precision, tol)
+    outs = []
+    for xy in (0, 256, 1024):
+        for glob, pad in ((E, case.E), (B, case.B), (J, case.J)):
+            case.plan.scatter([torch.from_numpy(np.ascontiguousarray(glob[a])).to("cuda", case.dtype).reshape(-1)
+                               for a in range(3)], pad)
+        case.plan.set_tuning(xy_threads=xy)
+        case.plan.run(case.E, case.B, case.J, 3)
+        case.plan.sync()
+        outs.append(torch.cat([x.clone() for x in case.E + case.B]))
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+    case.plan.set_tuning(batch_boxes=2)
+    assert case.plan.tuning()["xy_threads"] != 0
+    with pytest.raises(psatd.PsatdError):
+        case.plan.set_tuning(xy_threads=0)
