@@ -424,23 +424,29 @@ SPL_OF = {"f32": 0, "bf16x3": 2, "bf16x6": 3}
 
 def kernel_instance(phase, form, tuning):
     """The template instance (as the profiler prints it) that runs `phase` for
-    the FP32 form `form` with launch shapes `tuning` (unsplit x/y passes)."""
+    the FP32 form `form` with launch shapes `tuning` (unsplit x/y passes); with
+    per-class x/y launches (xy_threads 0) the group size is a wildcard `*`
+    standing for every class's instance."""
     spl = SPL_OF[form]
     maxr = 16 if spl else tuning["max_radix"]
     if phase == "z_update":
         pb = tuning["z_pencils"]
         nt = 512 if pb == 4 else tuning["z_threads"]
         return f"psatd::k_z_update<float, {nt}, {pb}, true, {maxr}, {spl}>"
+    nt = tuning["xy_threads"] or "*"
     if phase == "fft_xy_fwd":
-        return f"psatd::k_fwd_xy<float, {tuning['xy_threads']}, {maxr}, {spl}>"
+        return f"psatd::k_fwd_xy<float, {nt}, {maxr}, {spl}>"
     if phase == "fft_xy_inv":
-        return f"psatd::k_inv_xy<float, true, {tuning['xy_threads']}, {maxr}, {spl}>"
+        return f"psatd::k_inv_xy<float, true, {nt}, {maxr}, {spl}>"
     return "psatd::k_fill<float>"
 
 
 def read_traffic(workload, instance):
     """Scaled HBM bytes per dispatch of the kernel instance from the committed
-    summary, or None when there is none or it was taken on other sources."""
+    summary (summed over the matching instances when the name holds a `*`:
+    the per-class launches of one phase, one dispatch each), or None when there
+    is none or it was taken on other sources."""
+    import fnmatch
     path = traffic_path(workload)
     if not os.path.exists(path):
         return None
@@ -450,8 +456,8 @@ def read_traffic(workload, instance):
             digest = line.split(":", 1)[1].strip()
         elif line.startswith("kernel "):
             fields = [f.strip() for f in line[len("kernel "):].split("|")]
-            if fields[0] == instance:
-                found = float(fields[4])
+            if fnmatch.fnmatchcase(fields[0], instance.replace("[", "[[]")):
+                found = (found or 0.0) + float(fields[4])
     if digest != source_digest():
         return None
     return found

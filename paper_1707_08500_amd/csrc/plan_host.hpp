@@ -622,9 +622,14 @@ inline psatd_status build_host(HostTables& h, std::string& err, const int64_t gr
   // z-update tile: PB consecutive (ky, kx) pencils (128-byte rows when possible)
   {
     // 8 pencils (64-byte FP32 / 128-byte FP64 rows): two FP32 96^3 tiles fit a
-    // CU's LDS, so one tile's loads overlap the other's transforms
+    // CU's LDS, so one tile's loads overlap the other's transforms.  FP32
+    // tiles of longer z (176: 101 KB) would leave one tile per CU; 4 pencils
+    // keep three (configuration 5 z pass 35.5 -> 30.4 ms).  FP64 keeps 8:
+    // its 4-pencil tiles measured slower on 96^3 boxes.
     int PB = 8;
     while (PB > 4 && !z_tile_fits(h, maxPz, PB)) PB /= 2;
+    const int64_t tile8 = (int64_t)maxPz * (9 * 8 + 1) * 2 * real_size(precision) + maxPz * 4;
+    if (!f64 && PB == 8 && 2 * tile8 > kMaxDynLds) PB = 4;
     if (!z_tile_fits(h, maxPz, PB))
       return bad(PSATD_E_UNSUPPORTED, "padded z length too large for the z-update kernel");
     h.PB = PB;
