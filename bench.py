@@ -594,7 +594,31 @@ def roofline_block(wl_name, res, form, dec):
             "bytes_per_launch": bmin, "bytes_rule": "B_min = 15 reals x %d B x %d padded cells" % (sb, cells),
             "kernel_ms": phases[dom],
             "kernel_own": {"algorithmic_bytes": own, "achieved": own / t / 1e9,
-                           "frac": own / t / 1e9 / HBM_PEAK_GBS}}
+                           "frac": own / t / 1e9 / HBM_PEAK_GBS},
+            "copy_reference": COPY_REF}
+
+
+COPY_REF = None  # achievable device-copy rate of this GPU, measured once per run (copy_reference)
+
+
+def copy_reference():
+    """The rate of a plain 1 GiB device-to-device copy (torch's copy kernel;
+    read + write bytes over the event-timed mean of 10 copies): the practical
+    streaming ceiling next to the 8 TB/s specification peak."""
+    import torch
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbs = 2 * COPY_BYTES / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"GB/s": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS, "kernel": "torch copy_ of 1 GiB, 10 times"}
 
 
 def step_fractions(res, dec, sb):
@@ -723,6 +747,9 @@ def main():
         del src, dst
         log("[bench] copy calibration: 3 x 1 GiB device copies")
 
+    global COPY_REF
+    COPY_REF = copy_reference()
+    log(f"[bench] device copy: {COPY_REF['GB/s']:.0f} GB/s")
     wl = WORKLOADS[args.workload]
     N = wl["N"]
     d = (1.0, 1.0, 1.0)
