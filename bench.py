@@ -572,7 +572,7 @@ def rel_l2(a, ref):
 
 
 def roofline_block(wl_name, res, form, dec):
-    """roofline per the survey's measurement rule: the algorithmic minimum of
+    """roofline by the benchmark's measurement rule: the algorithmic minimum of
     a step, B_min = 15 reals (read E, B, J; write E, B) per padded cell, over
     the dominant kernel's event-timed launch; next to it the same kernel's own
     algorithmic bytes over the same time, and its HBM traffic from the

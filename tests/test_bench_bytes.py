@@ -64,7 +64,7 @@ def test_fp64_writes_without_reading_and_fused_exchange_moves_nothing():
 
 
 def test_roofline_block_is_bmin_over_the_dominant_kernel():
-    """roofline.achieved follows the survey's measurement rule: B_min = 15
+    """roofline.achieved follows the benchmark's measurement rule: B_min = 15
     reals (read E, B, J; write E, B) per padded cell per step, over the
     event-timed launch of the dominant kernel; the kernel's own algorithmic
     bytes over the same time are reported beside it."""

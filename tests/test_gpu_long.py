@@ -17,8 +17,8 @@ is compared with one FP64 oracle run of that input.  Bars, per component
 to the bound its arithmetic gives (two BF16 terms per operand leave about
 5 * 2^-18 of relative error per matrix-core product).
 
-Per-component errors are printed and, when a gpurun_out/ folder exists at the
-repository root, appended to gpurun_out/long_parity.jsonl.
+Per-component errors are printed and, when the environment names a file in
+PSATD_PARITY_LOG, appended to it as JSON lines.
 """
 import json
 import os
@@ -34,8 +34,7 @@ from psatd_cases import GpuCase, config2_fields, say
 
 pytestmark = pytest.mark.gpu
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-OUT = os.path.join(ROOT, "gpurun_out")
+OUT = os.environ.get("PSATD_PARITY_LOG")
 NAMES = ("Ex", "Ey", "Ez", "Bx", "By", "Bz")
 FORMS = ("f64", "f32", "bf16x6", "bf16x3")
 TOL = {"f64": 1e-12, "f32": 1e-5, "bf16x6": 1e-5, "bf16x3": 1e-3}
@@ -52,8 +51,8 @@ def _gpu():
 
 def record(row):
     say("  " + json.dumps(row))
-    if os.path.isdir(OUT):
-        with open(os.path.join(OUT, "long_parity.jsonl"), "a") as f:
+    if OUT:
+        with open(OUT, "a") as f:
             f.write(json.dumps(row) + "\n")
 
 
