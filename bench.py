@@ -425,12 +425,14 @@ SPL_OF = {"f32": 0, "bf16x3": 2, "bf16x6": 3}
 def kernel_instance(phase, form, tuning):
     """The template instance (as the profiler prints it) that runs `phase` for
     the FP32 form `form` with launch shapes `tuning` (unsplit x/y passes); with
-    per-class x/y launches (xy_threads 0) the group size is a wildcard `*`
-    standing for every class's instance."""
+    per-class launches (xy_threads or z_pencils 0) the class-dependent template
+    arguments are wildcards `*` standing for every class's instance."""
     spl = SPL_OF[form]
     maxr = 16 if spl else tuning["max_radix"]
     if phase == "z_update":
         pb = tuning["z_pencils"]
+        if pb == 0:  # per-class z launches: every tile size's instance
+            return f"psatd::k_z_update<float, *, *, true, {maxr}, {spl}>"
         nt = 512 if pb == 4 else tuning["z_threads"]
         return f"psatd::k_z_update<float, {nt}, {pb}, true, {maxr}, {spl}>"
     nt = tuning["xy_threads"] or "*"

@@ -61,6 +61,8 @@ struct HostTables {
   std::vector<int32_t> boxlds;     // dynamic LDS bytes of one x/y plane of each box
   std::vector<XyClass> xyc;       // x/y launch classes (empty: one launch for every box)
   std::vector<int32_t> itemsXYC;  // their work lists
+  std::vector<ZClass> zcls;       // z launch classes (empty: one tile size for every box)
+  std::vector<int32_t> itemsZC;   // their work lists
   std::vector<ZGroup> zgroups;    // one per distinct padded z length
   std::vector<int32_t> itemsZR;   // their work lists, nsub + 1 prefix entries each
 };
@@ -265,6 +267,61 @@ inline void set_z_tile(HostTables& h, int PB) {
 inline bool z_tile_fits(const HostTables& h, int maxPz, int PB) {
   const int csz = (int)(2 * real_size(h.prec));
   return (int64_t)maxPz * (9 * PB + 1) * csz + maxPz * 4 <= kMaxDynLds;
+}
+
+// Dynamic LDS of a z tile of PB pencils of padded z length Pz.
+inline int64_t z_tile_lds(const HostTables& h, int Pz, int PB) {
+  return (int64_t)Pz * (9 * PB + 1) * (int64_t)(2 * real_size(h.prec)) + (int64_t)Pz * 4;
+}
+
+// Pencils per z tile of one box on its own: 8 (64-byte FP32 / 128-byte FP64
+// rows) where two FP32 tiles (one FP64 tile) of the box fit a compute unit's
+// LDS, else 4; 0 when not even a 4-pencil tile fits.
+inline int z_pencils_for(const HostTables& h, int Pz) {
+  const int64_t t8 = z_tile_lds(h, Pz, 8);
+  if ((is_f64(h.prec) ? t8 : 2 * t8) <= kMaxDynLds) return 8;
+  return z_tile_lds(h, Pz, 4) <= kMaxDynLds ? 4 : 0;
+}
+
+// Launch classes of the z pass: boxes grouped by their own tile size, each
+// class launched with the LDS of its longest padded z, so the short-z boxes
+// of an uneven decomposition keep 8-pencil tiles, two per compute unit, next
+// to 4-pencil tiles of the long ones.  None when every box takes one size.
+inline void build_z_classes(HostTables& h) {
+  h.zcls.clear();
+  h.itemsZC.clear();
+  std::vector<int> pb(h.nsub);
+  int used = 0;
+  for (int s = 0; s < h.nsub; ++s) {
+    pb[s] = z_pencils_for(h, h.box[s].P[2]);
+    if (!pb[s]) return;
+    used |= pb[s] == 8 ? 1 : 2;
+  }
+  if (used != 3) return;
+  for (int PB : {8, 4}) {
+    ZClass k{};
+    k.PB = PB;
+    k.U = (int32_t)h.itemsZC.size();
+    int32_t acc = 0;
+    h.itemsZC.push_back(0);
+    for (int s = 0; s < h.nsub; ++s) {
+      const BoxD& b = h.box[s];
+      if (pb[s] == PB) {
+        acc += (int32_t)(((int64_t)b.P[1] * b.H + PB - 1) / PB);
+        k.lds = std::max<int32_t>(k.lds, (int32_t)z_tile_lds(h, b.P[2], PB));
+      }
+      h.itemsZC.push_back(acc);
+    }
+    k.nU = acc;
+    h.zcls.push_back(k);
+  }
+}
+
+// The largest dynamic LDS any z launch of the plan may ask for.
+inline int32_t z_lds_max(const HostTables& h) {
+  int32_t m = h.ldsU;
+  for (const ZClass& k : h.zcls) m = std::max(m, k.lds);
+  return m;
 }
 
 // Re-derives every FFT schedule with radices up to maxr (twiddle tables
@@ -678,6 +735,7 @@ inline psatd_status build_host(HostTables& h, std::string& err, const int64_t gr
   h.ntu = 512;
   h.ntxy = xy_threads_for(h.ldsF);
   build_xy_classes(h);
+  build_z_classes(h);
   if (f64 && !set_max_radix(h, 8)) return bad(PSATD_E_UNSUPPORTED, "no radix-8 schedule");
   return PSATD_OK;
 }

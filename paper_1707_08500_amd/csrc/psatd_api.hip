@@ -329,6 +329,7 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   const size_t o_pull = reserve(std::max<size_t>(h.pullp.size(), 1) * sizeof(PullPiece));
   const size_t o_poff = reserve(h.pull_off.size() * 4);
   const size_t o_xyc = reserve(std::max<size_t>(h.itemsXYC.size(), 1) * 4);
+  const size_t o_zc = reserve(std::max<size_t>(h.itemsZC.size(), 1) * 4);
   std::vector<unsigned char> hb(total, 0);
   auto put = [&](size_t off, const void* src, size_t bytes) {
     if (bytes) std::memcpy(hb.data() + off, src, bytes);
@@ -359,13 +360,15 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   put(o_pull, h.pullp.data(), h.pullp.size() * sizeof(PullPiece));
   put(o_poff, h.pull_off.data(), h.pull_off.size() * 4);
   put(o_xyc, h.itemsXYC.data(), h.itemsXYC.size() * 4);
+  put(o_zc, h.itemsZC.data(), h.itemsZC.size() * 4);
   if ((e = hipMalloc(&p->blob, total)) != hipSuccess) return hipfail(e, "hipMalloc(tables)");
   if ((e = hipMemcpy(p->blob, hb.data(), total, hipMemcpyHostToDevice)) != hipSuccess)
     return hipfail(e, "hipMemcpy(tables)");
   if ((e = hipMalloc(&p->d_itemsU, h.itemsU.size() * 4)) != hipSuccess) return hipfail(e, "hipMalloc(work list)");
   if ((e = hipMemcpy(p->d_itemsU, h.itemsU.data(), h.itemsU.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
     return hipfail(e, "hipMemcpy(work list)");
-  p->tune[PSATD_TUNE_Z_PENCILS] = h.PB;
+  // boxes of several tile sizes: one z launch per class (z_pencils 0)
+  p->tune[PSATD_TUNE_Z_PENCILS] = h.zcls.empty() ? h.PB : 0;
   p->tune[PSATD_TUNE_MAX_RADIX] = h.maxr;
   // boxes of several plane sizes: one x/y launch per class (xy_threads 0)
   p->tune[PSATD_TUNE_XY_THREADS] = h.xyc.size() > 1 ? 0 : h.ntxy;
@@ -377,7 +380,7 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
                        reinterpret_cast<double*>(B + o_kmod), p->cap_stream)) != hipSuccess)
     return hipfail(e, "modified-wavenumber kernel");
   if ((e = hipStreamSynchronize(p->cap_stream)) != hipSuccess) return hipfail(e, "modified-wavenumber kernel");
-  if ((e = prepare_kernels(f64, h.spl, h.ldsF, h.ldsI, h.ldsU, h.ldsX, h.ldsY)) != hipSuccess)
+  if ((e = prepare_kernels(f64, h.spl, h.ldsF, h.ldsI, z_lds_max(h), h.ldsX, h.ldsY)) != hipSuccess)
     return hipfail(e, "hipFuncSetAttribute");
 
   DevPlan& d = p->dp;
@@ -436,6 +439,10 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   d.ldsI = h.ldsI;
   d.ldsU = h.ldsU;
   d.PB = h.PB;
+  d.zcl = h.zcls.empty() ? 0 : 1;
+  d.nzc = (int32_t)h.zcls.size();
+  for (int i = 0; i < d.nzc; ++i) d.zc[i] = h.zcls[i];
+  d.itemsZC = reinterpret_cast<const int32_t*>(B + o_zc);
   d.ldsH = heat_lds(h);
   d.ntu = h.ntu;
   d.ntxy = p->tune[PSATD_TUNE_XY_THREADS];
@@ -669,13 +676,22 @@ psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
   DevPlan& d = p->dp;
   switch (key) {
     case PSATD_TUNE_Z_PENCILS: {
-      if (value != 4 && value != 8 && value != 16) return fail(p, PSATD_E_INVALID, "z pencils must be 4, 8 or 16");
+      if (value == 0) {  // one launch per class of tile size
+        if (p->h.zcls.empty() || p->h.batches.size() > 1)
+          return fail(p, PSATD_E_INVALID,
+                      "per-class z launches need an unbatched plan whose boxes take several tile sizes");
+        d.zcl = 1;
+        break;
+      }
+      if (value != 4 && value != 8 && value != 16)
+        return fail(p, PSATD_E_INVALID, "z pencils must be 0 (per launch class), 4, 8 or 16");
       if (!z_tile_fits(p->h, max_padded_z(p->h), value))
         return fail(p, PSATD_E_INVALID, "z tile does not fit the LDS");
       HIPCHK(p, hipStreamSynchronize(p->stream));
       set_z_tile(p->h, value);
       HIPCHK(p, hipMemcpy(p->d_itemsU, p->h.itemsU.data(), p->h.itemsU.size() * 4, hipMemcpyHostToDevice));
-      HIPCHK(p, prepare_kernels(d.f64, d.spl, p->h.ldsF, p->h.ldsI, p->h.ldsU, p->h.ldsX, p->h.ldsY));
+      HIPCHK(p, prepare_kernels(d.f64, d.spl, p->h.ldsF, p->h.ldsI, z_lds_max(p->h), p->h.ldsX, p->h.ldsY));
+      d.zcl = 0;
       d.PB = p->h.PB;
       d.ldsU = p->h.ldsU;
       d.ldsH = heat_lds(p->h);
@@ -710,6 +726,10 @@ psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
         if (d.ntxy == 0) {  // batches launch every box of a batch with one group size
           d.ntxy = p->h.ntxy;
           p->tune[PSATD_TUNE_XY_THREADS] = p->h.ntxy;
+        }
+        if (d.zcl) {  // and one tile size
+          d.zcl = 0;
+          p->tune[PSATD_TUNE_Z_PENCILS] = p->h.PB;
         }
       }
       break;
@@ -868,7 +888,7 @@ psatd_status psatd_autotune(psatd_plan_t p, void* const E[3], void* const B[3], 
         // 0: one launch per class of plane size, for uneven boxes of an unbatched plan
         if (xy == 0 && (p->h.xyc.size() < 2 || p->h.batches.size() > 1)) continue;
         if ((r = psatd_set_tuning(p, PSATD_TUNE_XY_THREADS, xy)) != PSATD_OK) return r;
-        for (int pb : {16, 8, 4}) {
+        for (int pb : {0, 16, 8, 4}) {  // 0: per class of tile size, when the plan has classes
           if (psatd_set_tuning(p, PSATD_TUNE_Z_PENCILS, pb) != PSATD_OK) continue;
           for (int zt : {512, 1024}) {
             if ((r = psatd_set_tuning(p, PSATD_TUNE_Z_THREADS, zt)) != PSATD_OK) return r;

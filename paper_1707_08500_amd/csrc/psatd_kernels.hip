@@ -365,21 +365,26 @@ hipError_t launch_fwd(const DevPlan& p, const Batch& b, void* const* in9, void* 
   return p.f64 ? fwd_t<double>(p, b, in9, spec, st, scalar) : fwd_t<float>(p, b, in9, spec, st, scalar);
 }
 
+// One z launch: n items from item0, PB pencils per tile, lds bytes of LDS.
+struct UpdLaunch {
+  int g, PB, lds, item0, n;
+};
+
 template <typename T, int NT, int PB, int MAXR, int SPL>
-static hipError_t upd_launch(const DevPlan& p, const Batch& b, const UpdArgs<T>& a, int g, hipStream_t st) {
-  hipLaunchKernelGGL((k_z_update<T, NT, PB, IncOf<T>::value, MAXR, SPL>), dim3(g), dim3(NT), p.ldsU, st, a,
-                     b.U0, b.nU, p.xcd);
+static hipError_t upd_launch(const DevPlan& p, const UpdLaunch& l, const UpdArgs<T>& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_z_update<T, NT, PB, IncOf<T>::value, MAXR, SPL>), dim3(l.g), dim3(NT), l.lds, st, a,
+                     l.item0, l.n, p.xcd);
   return hipGetLastError();
 }
 
 template <typename T, int MAXR, int SPL>
-static hipError_t upd_shape(const DevPlan& p, const Batch& b, const UpdArgs<T>& a, int g, hipStream_t st) {
-  if (p.PB == 4) return upd_launch<T, 512, 4, MAXR, SPL>(p, b, a, g, st);
+static hipError_t upd_shape(const DevPlan& p, const UpdLaunch& l, const UpdArgs<T>& a, hipStream_t st) {
+  if (l.PB == 4) return upd_launch<T, 512, 4, MAXR, SPL>(p, l, a, st);
   if (p.ntu == 1024)
-    return p.PB == 16 ? upd_launch<T, 1024, 16, MAXR, SPL>(p, b, a, g, st)
-                      : upd_launch<T, 1024, 8, MAXR, SPL>(p, b, a, g, st);
-  return p.PB == 16 ? upd_launch<T, 512, 16, MAXR, SPL>(p, b, a, g, st)
-                    : upd_launch<T, 512, 8, MAXR, SPL>(p, b, a, g, st);
+    return l.PB == 16 ? upd_launch<T, 1024, 16, MAXR, SPL>(p, l, a, st)
+                      : upd_launch<T, 1024, 8, MAXR, SPL>(p, l, a, st);
+  return l.PB == 16 ? upd_launch<T, 512, 16, MAXR, SPL>(p, l, a, st)
+                    : upd_launch<T, 512, 8, MAXR, SPL>(p, l, a, st);
 }
 
 template <typename T>
@@ -391,14 +396,28 @@ static hipError_t upd_t(const DevPlan& p, const Batch& b, void* spec, hipStream_
   a.sbias = b.sbias;
   a.k.c = p.c;
   a.k.dt = p.dt;
+  auto go = [&](const UpdLaunch& l) -> hipError_t {
+    return with_spl<T>(p.spl, [&](auto sc) -> hipError_t {
+      constexpr int SPL = decltype(sc)::value;
+      PSATD_MAXR_SWITCH(SPL, return (upd_shape<T, 8, SPL>(p, l, a, st)),
+                        return (upd_shape<T, 16, SPL>(p, l, a, st)));
+      return hipSuccess;
+    });
+  };
+  if (p.zcl) {  // one launch per class of tile size (unbatched plans only)
+    for (int c = 0; c < p.nzc; ++c) {
+      const ZClass& k = p.zc[c];
+      a.items = p.itemsZC + k.U;
+      const int g = grid_for(k.nU, p.grid_cap[kPhaseUpd]);
+      if (!g) continue;
+      const hipError_t e = go(UpdLaunch{g, k.PB, k.lds, 0, k.nU});
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   const int g = grid_for(b.nU, p.grid_cap[kPhaseUpd]);
   if (!g) return hipSuccess;
-  return with_spl<T>(p.spl, [&](auto sc) -> hipError_t {
-    constexpr int SPL = decltype(sc)::value;
-    PSATD_MAXR_SWITCH(SPL, return (upd_shape<T, 8, SPL>(p, b, a, g, st)),
-                      return (upd_shape<T, 16, SPL>(p, b, a, g, st)));
-    return hipSuccess;
-  });
+  return go(UpdLaunch{g, p.PB, p.ldsU, b.U0, b.nU});
 }
 
 hipError_t launch_upd(const DevPlan& p, const Batch& b, void* spec, hipStream_t st) {

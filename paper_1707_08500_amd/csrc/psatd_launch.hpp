@@ -42,7 +42,11 @@ struct DevPlan {
   int32_t nF, nU, nI, nP, nN;
   int32_t ldsF, ldsI, ldsU;  // dynamic LDS bytes per work-group
   int32_t ldsH;              // heat z pass: one staged field
-  int32_t PB;                // pencils per z-update work-group
+  int32_t PB;                // pencils per z-update work-group (one size for every box)
+  int32_t zcl;               // 1: one z launch per class of tile size (below)
+  int32_t nzc;
+  ZClass zc[kMaxZClasses];
+  const int32_t* itemsZC;
   int32_t ntu;               // threads per z-update work-group (512 or 1024)
   int32_t ntxy;              // threads per x/y work-group (256, 512 or 1024; 0: per launch class)
   int32_t nxyc;              // x/y launch classes (used when ntxy == 0)

@@ -192,10 +192,31 @@ bool check_tables(const Dec& d, const HostTables& h, bool pieces = true) {
     }
     CHECK(tf == h.itemsF.back() && ti == h.itemsI.back(), "%s: class work lists add up", d.name.c_str());
   }
+  // z launch classes: every box in exactly one, with all its tiles, within the class's LDS
+  if (!h.zcls.empty()) {
+    CHECK(h.zcls.size() == 2, "%s: z class count", d.name.c_str());
+    for (int s = 0; s < nsub; ++s) {
+      int in = 0;
+      for (const ZClass& k : h.zcls) {
+        const int32_t* U = h.itemsZC.data() + k.U;
+        const int cu = U[s + 1] - U[s];
+        if (!cu) continue;
+        ++in;
+        CHECK(k.PB == z_pencils_for(h, h.box[s].P[2]), "%s: z class of box %d", d.name.c_str(), s);
+        CHECK(cu == (h.box[s].P[1] * h.box[s].H + k.PB - 1) / k.PB, "%s: z class work of box %d", d.name.c_str(), s);
+        CHECK(z_tile_lds(h, h.box[s].P[2], k.PB) <= k.lds && k.lds <= kMaxDynLds, "%s: z class LDS of box %d",
+              d.name.c_str(), s);
+      }
+      CHECK(in == 1, "%s: box %d in %d z classes", d.name.c_str(), s, in);
+    }
+    CHECK(h.itemsZC[h.zcls[0].U + nsub] == h.zcls[0].nU && h.itemsZC[h.zcls[1].U + nsub] == h.zcls[1].nU,
+          "%s: z class totals", d.name.c_str());
+  }
   return true;
 }
 
-int g_classes = 0;  // built plans with several x/y launch classes
+int g_classes = 0;   // built plans with several x/y launch classes
+int g_zclasses = 0;  // built plans with two z launch classes
 
 int run_case(const Dec& d, int prec, int jmode, int p, bool expect_ok, int& built) {
   HostTables h;
@@ -221,6 +242,7 @@ int run_case(const Dec& d, int prec, int jmode, int p, bool expect_ok, int& buil
   }
   ++built;
   if (!h.xyc.empty()) ++g_classes;
+  if (!h.zcls.empty()) ++g_zclasses;
   if (!check_tables(d, h)) return 0;
   // the launch-shape knobs that rebuild host tables
   const int maxPz = max_padded_z(h);
@@ -263,6 +285,12 @@ int main() {
     const int64_t N[3] = {192, 64, 48};
     std::vector<int64_t> cuts[3] = {{0, 32, 192}, {0, 64}, {0, 16, 48}};
     ok.push_back(tiled("x/y launch classes", N, cuts, {8, 8, 8, 8, 8, 8}));
+  }
+  {
+    // padded z lengths of 128 and 160: 8- and 4-pencil FP32 z tiles
+    const int64_t N[3] = {32, 32, 256};
+    std::vector<int64_t> cuts[3] = {{0, 32}, {0, 32}, {0, 112, 256}};
+    ok.push_back(tiled("z launch classes", N, cuts, {8, 8, 8, 8, 8, 8}));
   }
   {
     const int64_t N[3] = {20, 21, 15};
@@ -338,11 +366,11 @@ int main() {
       ++g_fail;
     }
   }
-  if (g_fail || built < 30 || passed != built || g_classes == 0) {
+  if (g_fail || built < 30 || passed != built || g_classes == 0 || g_zclasses == 0) {
     std::fprintf(stderr, "plan_check: FAILED (%d failures, %d built, %d passed)\n", g_fail, built, passed);
     return 1;
   }
-  std::printf("plan_check: ok (%d decompositions x forms built and checked, %d with x/y launch classes, "
-              "%zu invalid rejected)\n", built, g_classes, bad.size());
+  std::printf("plan_check: ok (%d decompositions x forms built and checked, %d with x/y and %d with z launch "
+              "classes, %zu invalid rejected)\n", built, g_classes, g_zclasses, bad.size());
   return 0;
 }

@@ -743,3 +743,39 @@ def test_xy_launch_classes(precision, tol):
     assert case.plan.tuning()["xy_threads"] != 0
     with pytest.raises(psatd.PsatdError):
         case.plan.set_tuning(xy_threads=0)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_z_launch_classes(precision, tol):
+    """Subdomains whose padded z lengths take different z tiles (128: 8
+    pencils; 160: 4) run the z pass as one launch per class (the default,
+    z_pencils 0): the step matches the oracle (Sec. 3.2, Fig. 3 with the
+    update of Sec. 3.1) and is byte-identical to one launch of every box with
+    4-pencil tiles; the knob rejects 0 once the plan is batched."""
+    import torch
+    from paper_1707_08500_amd import psatd
+    say(f"z launch classes, {precision}")
+    N = (32, 32, 256)
+    lo = [[0, 0, 0], [0, 0, 112]]
+    n = [[32, 32, 112], [32, 32, 144]]
+    g = [[8, 8, 8]] * 2
+    E, B, J = random_fields(N, 37, p=16)
+    if precision == "f32":
+        E, B, J = (x.astype(np.float32).astype(np.float64) for x in (E, B, J))
+    case, eE, eB, _ = run_both(N, lo, n, g, 16, 0.5, 1.0, precision, "replicated", (E, B, J), 3)
+    assert case.plan.tuning()["z_pencils"] == 0
+    check(case, eE, eB, precision, tol)
+    outs = []
+    for pb in (0, 4):
+        for glob, pad in ((E, case.E), (B, case.B), (J, case.J)):
+            case.plan.scatter([torch.from_numpy(np.ascontiguousarray(glob[a])).to("cuda", case.dtype).reshape(-1)
+                               for a in range(3)], pad)
+        case.plan.set_tuning(z_pencils=pb)
+        case.plan.run(case.E, case.B, case.J, 3)
+        case.plan.sync()
+        outs.append(torch.cat([x.clone() for x in case.E + case.B]))
+    assert torch.equal(outs[0], outs[1])
+    case.plan.set_tuning(batch_boxes=1)
+    assert case.plan.tuning()["z_pencils"] != 0
+    with pytest.raises(psatd.PsatdError):
+        case.plan.set_tuning(z_pencils=0)
