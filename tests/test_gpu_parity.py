@@ -730,15 +730,18 @@ def test_xy_launch_classes(precision, tol):
     assert case.plan.tuning()["xy_threads"] == 0
     check(case, eE, eB, precision, tol)
     outs = []
-    for xy in (0, 256, 1024):
+    # per-class launches, single launches of 256 and 1024 threads, and per-class
+    # launches with the E,B exchange fused into the inverse pass
+    for xy, fuse in ((0, 0), (256, 0), (1024, 0), (0, 1)):
         for glob, pad in ((E, case.E), (B, case.B), (J, case.J)):
             case.plan.scatter([torch.from_numpy(np.ascontiguousarray(glob[a])).to("cuda", case.dtype).reshape(-1)
                                for a in range(3)], pad)
-        case.plan.set_tuning(xy_threads=xy)
+        case.plan.set_tuning(xy_threads=xy, fuse_eb=fuse)
         case.plan.run(case.E, case.B, case.J, 3)
         case.plan.sync()
         outs.append(torch.cat([x.clone() for x in case.E + case.B]))
-    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+    assert all(torch.equal(outs[0], o) for o in outs[1:])
+    case.plan.set_tuning(fuse_eb=0)
     case.plan.set_tuning(batch_boxes=2)
     assert case.plan.tuning()["xy_threads"] != 0
     with pytest.raises(psatd.PsatdError):
