@@ -118,3 +118,14 @@ def test_field_diagnostics_vanish_on_oracle_steps_and_see_a_planted_error():
     bad = bench.field_diagnostics(final, Inputs(), kt, steps * dt, c, dev="cpu")
     assert bad["gauss_rel"] > 1e-5
     assert bad["div_B_rel"] < 1e-13
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark is the single-GPU share of a sharded run: --gpus above 1
+    exits with status 2 and says so, before touching a device."""
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
