@@ -21,9 +21,11 @@
  * Conventions for every array argument below:
  *   - 3-vectors of sizes are ordered (x, y, z);
  *   - a "field buffer" is ONE device buffer per vector component (E[0..2] = Ex, Ey, Ez,
- *     and likewise B and J).  It holds every subdomain's PADDED box back to back, in
- *     subdomain order; box s starts at element offset(s) (see psatd_field_layout) and is
- *     stored C-ordered [z][y][x] (x fastest) with extents n(s) + 2 guard(s).  The
+ *     and likewise B and J).  It holds every subdomain's PADDED box in subdomain order;
+ *     box s starts at element offset(s) (see psatd_field_layout) and is stored C-ordered
+ *     [z][y][x] (x fastest) with extents n(s) + 2 guard(s).  Consecutive boxes are
+ *     separated by a gap of less than 128 bytes, chosen so that each box's first interior
+ *     x cell starts a 128-byte line (the kernels never touch the gaps).  The
  *     element type is double for PSATD_F64 and float for every other precision.
  *     Buffers must be 16-byte aligned (torch allocations are).
  *   - a "global buffer" is one device buffer per component holding the interior grid,
@@ -166,7 +168,8 @@ psatd_status psatd_validate(const int64_t grid_n[3], const double grid_d[3], int
                             int32_t order_p, double dt, double c, int32_t precision,
                             int32_t jmode, int64_t* field_elems);
 
-/* Elements of one field buffer (= sum over subdomains of the padded volume). */
+/* Elements of one field buffer: the padded volumes of all subdomains plus the alignment
+ * gaps between them (the last box ends the buffer). */
 psatd_status psatd_field_elems(psatd_plan_t plan, int64_t* total);
 
 /* Padded extents (x, y, z) of subdomain s and its element offset in a field buffer. */

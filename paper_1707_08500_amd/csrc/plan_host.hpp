@@ -653,6 +653,16 @@ inline psatd_status build_host(HostTables& h, std::string& err, const int64_t gr
     b.kx = add_kentry(h, b.P[0], grid_d[0]);
     b.ky = add_kentry(h, b.P[1], grid_d[1]);
     b.kz = add_kentry(h, b.P[2], grid_d[2]);
+    // The box starts where its first interior x cell begins a 128-byte line
+    // (to within the 16 bytes that keep vector accesses aligned): then the
+    // interior rows, and the guard rows pulled from them, are whole lines
+    // whenever the row pitch is.  The gap costs under 128 bytes per box.
+    {
+      const int64_t line = 128 / (int64_t)real_size(precision), vec = 16 / (int64_t)real_size(precision);
+      const int64_t t = (line - b.g[0] % line) % line;
+      const int64_t want = (t + vec - 1) / vec * vec % line;
+      foff += ((want - foff) % line + line) % line;
+    }
     b.foff = foff;
     b.soff = soff;
     b.svol = (int64_t)b.H * b.P[1] * b.P[2];

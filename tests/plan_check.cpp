@@ -11,7 +11,8 @@
 //   * every piece's first and last element lie inside its source and
 //     destination boxes' field ranges, and the pull list is the push list
 //     regrouped by destination;
-//   * the work-list prefixes and spectral offsets add up;
+//   * the work-list prefixes and spectral offsets add up, and the boxes' field
+//     offsets are ordered, aligned and closely packed;
 // then it re-tiles the z pass, re-batches and re-schedules the radices.
 // Invalid decompositions must be rejected with an error, not undefined
 // behaviour.  Prints "plan_check: ok ..." and exits 0, or names the first
@@ -89,9 +90,15 @@ bool check_tables(const Dec& d, const HostTables& h, bool pieces = true) {
     return -1;
   };
   int64_t foff = 0, soff = 0;
+  const int64_t line = 128 / (int64_t)real_size(h.prec), vec = 16 / (int64_t)real_size(h.prec);
   for (int s = 0; s < nsub; ++s) {
     const BoxD& b = h.box[s];
-    CHECK(b.foff == foff && b.soff == soff, "%s: box %d offsets", d.name.c_str(), s);
+    // boxes in order, no overlap, a gap of less than one line, 16-byte
+    // aligned, the first interior x cell within 16 bytes of a line start
+    CHECK(b.foff >= foff && b.foff - foff < line && b.foff % vec == 0 && (b.foff + b.g[0]) % line < vec &&
+              b.soff == soff,
+          "%s: box %d offsets", d.name.c_str(), s);
+    foff = b.foff;
     CHECK(b.svol == (int64_t)b.H * b.P[1] * b.P[2], "%s: box %d svol", d.name.c_str(), s);
     foff += (int64_t)b.P[0] * b.P[1] * b.P[2];
     soff += b.svol;

@@ -55,10 +55,16 @@ def deposited_partition(J, dec, seed):
 
 
 def upload_boxes(case, bufs, boxes):
-    """Writes per-box padded arrays (3, Pz, Py, Px) into a plan's field buffers."""
+    """Writes per-box padded arrays (3, Pz, Py, Px) into a plan's field buffers,
+    each box at the offset the plan's layout gives it (the alignment gaps
+    between boxes stay zero)."""
     import torch
     for a in range(3):
-        host = np.concatenate([boxes[s][a].ravel() for s in range(case.dec.nsub)])
+        host = np.zeros(case.plan.field_elems)
+        for s in range(case.dec.nsub):
+            _, off = case.plan.layout(s)
+            flat = boxes[s][a].ravel()
+            host[off:off + flat.size] = flat
         bufs[a].copy_(torch.from_numpy(host).to("cuda", case.dtype))
     torch.cuda.synchronize()
 

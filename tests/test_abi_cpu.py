@@ -44,17 +44,21 @@ def good_case():
 
 def test_validate_accepts_config2_layout():
     from paper_1707_08500_amd import psatd
+    # boxes back to back except for the gap (< one 128-byte line) that starts
+    # each box's first interior x cell on a line: none in FP64 with 16 guards
+    # (16 doubles = one line), 16 floats before the first box in FP32
     elems = psatd.validate(**good_case())
     assert elems == 64 * 96 ** 3
     elems32 = psatd.validate(**good_case(), precision="f32")
-    assert elems32 == elems
+    assert elems32 == elems + 16
 
 
 def test_validate_uneven_decomposition():
     from paper_1707_08500_amd import psatd
     lo, n, g = synth.uneven_decomposition((512, 512, 256), case=4)
     elems = psatd.validate((512, 512, 256), (1.0, 1.0, 1.0), lo, n, g, 64, 0.5, precision="f32")
-    assert elems == int(np.prod(n + 2 * g, axis=1).sum())
+    vol = int(np.prod(n + 2 * g, axis=1).sum())
+    assert vol <= elems < vol + 32 * len(n)
 
 
 @pytest.mark.parametrize("mutate,status", [

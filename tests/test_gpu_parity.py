@@ -89,10 +89,7 @@ def run_both(N, lo, n, g, p, dt, c, precision, jmode, fields, steps, d=(1.0, 1.0
         got = case.plan.tuning()
         assert all(got[k] == v for k, v in tuning.items()), got
     if J_boxes is not None:  # deposited partial currents per copy
-        import torch
-        for a in range(3):
-            host = np.concatenate([J_boxes[s][a].ravel() for s in range(case.dec.nsub)])
-            case.J[a].copy_(torch.from_numpy(host).to("cuda", case.dtype))
+        upload_boxes(case, case.J, J_boxes)
     case.plan.run(case.E, case.B, case.J, steps)
     case.plan.sync()
     dec = case.dec
