@@ -146,6 +146,46 @@ def test_step_uneven_deposited(precision, tol):
     assert max(jerr) <= (1e-14 if precision == "f64" else 1e-6)
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_box_offsets_aligned_and_gaps_untouched(precision):
+    """Each box starts where its first interior x cell begins a 128-byte line
+    (to within 16 bytes), boxes keep their order with gaps of under one line,
+    and no pass (scatter, pulled or copied or fused E,B exchange, steps,
+    gather) writes into the gaps: a sentinel there survives bit for bit."""
+    import torch
+    say(f"box offsets and gaps {precision}")
+    N, lo, n, g = uneven_small()
+    E, B, J = random_fields(N, 11, p=4)
+    case = GpuCase(N, lo, n, g, 4, 0.3, 1.0, precision, "replicated", E, B, J)
+    plan = case.plan
+    sb = 8 if precision == "f64" else 4
+    line, vec = 128 // sb, 16 // sb
+    inside = np.zeros(plan.field_elems, dtype=bool)
+    end = 0
+    for s in range(case.dec.nsub):
+        (px, py, pz), off = plan.layout(s)
+        assert end <= off < end + line and off % vec == 0 and (off + int(g[s][0])) % line < vec, s
+        inside[off:off + px * py * pz] = True
+        end = off + px * py * pz
+    assert end == plan.field_elems and not inside.all()
+    gaps = torch.from_numpy(~inside).to("cuda")
+    sentinel = 7777.0
+    for bufs in (case.E, case.B, case.J):
+        for b in bufs:
+            b.masked_fill_(gaps, sentinel)
+    plan.run(case.E, case.B, case.J, 2)                  # pulled E,B guards
+    plan.set_tuning(fuse_eb=1)
+    plan.run(case.E, case.B, case.J, 1)                  # exchange fused into the inverse pass
+    plan.set_tuning(fuse_eb=0, pull_eb=0)
+    plan.run(case.E, case.B, case.J, 1)                  # exchange as a copy pass every step
+    plan.step_noalloc(case.E, case.B, case.J)
+    case.gathered(case.E)
+    plan.sync()
+    for name, bufs in (("E", case.E), ("B", case.B), ("J", case.J)):
+        for a, b in enumerate(bufs):
+            assert bool((b[gaps] == sentinel).all()), f"{name}[{a}] gap written"
+
+
 def test_step_infinite_order_and_odd_lengths():
     """p = infinity; padded lengths 2*3*5, 7, 11 on uneven axes."""
     say("p=inf odd radices")
