@@ -430,6 +430,7 @@ def kernel_instance(phase, form, tuning):
     spl = SPL_OF[form]
     maxr = 16 if spl else tuning["max_radix"]
     if phase == "z_update":
+        maxr = 16 if spl else tuning.get("max_radix_z", maxr)
         pb = tuning["z_pencils"]
         if pb == 0:  # per-class z launches: every tile size's instance
             return f"psatd::k_z_update<float, *, *, true, {maxr}, {spl}>"

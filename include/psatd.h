@@ -107,8 +107,9 @@ typedef enum {
   PSATD_TUNE_GRID_EXCH = 5,  /* same for the guard exchanges */
   PSATD_TUNE_BATCH_BOXES = 6, /* subdomains pushed through the FFT/update passes together (0 = all);
                                  the workspace then holds one batch's half spectra */
-  PSATD_TUNE_MAX_RADIX = 7,   /* largest radix of the FFT schedules: 16, or 8 (fewer registers, more
-                                 stages); radix 11 is always allowed */
+  PSATD_TUNE_MAX_RADIX = 7,   /* largest radix of the x/y passes' FFT schedules: 16, or 8 (fewer
+                                 registers, more stages); radix 11 is always allowed.  Default 16, and 8
+                                 for FP64 plans whose planes fit the LDS */
   PSATD_TUNE_XY_THREADS = 8,  /* threads per work-group of the x/y passes: 256, 512 or 1024 for every
                                  subdomain; 0 (default for unbatched plans whose subdomains differ in how
                                  many padded planes fit a compute unit's LDS): one launch per such class,
@@ -129,7 +130,8 @@ typedef enum {
                                  so the E,B guard exchange runs once, after the run's last step (the state
                                  is consistent again on return, and every value is the one the exchange
                                  would have copied); 0: the exchange after every step */
-  PSATD_NTUNE = 14
+  PSATD_TUNE_MAX_RADIX_Z = 14, /* the same for the z pass's schedules; default 16 */
+  PSATD_NTUNE = 15
 } psatd_tune_key;
 
 /*

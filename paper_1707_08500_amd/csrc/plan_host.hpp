@@ -53,7 +53,9 @@ struct HostTables {
   int64_t field_elems = 0;
   int64_t slab = 0;
   int ldsF = 0, ldsI = 0, ldsU = 0, PB = 0;
-  int maxr = 16;      // largest radix used by the FFT schedules (8 or 16; 11 always)
+  int maxr = 16;      // largest radix of the x/y schedules (8 or 16; 11 always)
+  int maxrz = 16;     // largest radix of the z schedules
+  std::vector<char> plan_z;  // per plan: 1 if it is a z schedule
   int spl = 0;        // BF16 terms of the matrix-core first stage (0: VALU form)
   int ntxy = 512;     // threads per work-group of the x/y passes
   int ntu = 512;      // threads per work-group of the z-update (1024 for FP32 by default)
@@ -180,12 +182,14 @@ inline void write_plan_twiddles(HostTables& h, FftPlanD& pl) {
   }
 }
 
-// Adds (or finds) an FFT plan of length N; returns its index or -1.
-inline int add_plan(HostTables& h, int N) {
+// Adds (or finds) an FFT plan of length N for the x/y passes or (zp) the z
+// pass, which keep schedules of their own (each pass has its largest radix);
+// returns its index or -1.
+inline int add_plan(HostTables& h, int N, bool zp) {
   for (size_t i = 0; i < h.plans.size(); ++i)
-    if (h.plans[i].N == N) return (int)i;
+    if (h.plans[i].N == N && (h.plan_z[i] != 0) == zp) return (int)i;
   std::vector<int> rad;
-  if (!schedule(N, rad, h.maxr, h.spl)) return -1;
+  if (!schedule(N, rad, zp ? h.maxrz : h.maxr, h.spl)) return -1;
   FftPlanD pl{};
   pl.N = N;
   set_stages(pl, rad);
@@ -194,6 +198,7 @@ inline int add_plan(HostTables& h, int N) {
   h.twi.resize(h.twi.size() + N);
   write_plan_twiddles(h, pl);
   h.plans.push_back(pl);
+  h.plan_z.push_back(zp ? 1 : 0);
   return (int)h.plans.size() - 1;
 }
 
@@ -327,16 +332,17 @@ inline int32_t z_lds_max(const HostTables& h) {
 // Re-derives every FFT schedule with radices up to maxr (twiddle tables
 // depend on the length only and are kept).  False if a length has no
 // schedule of at most kMaxStages stages.
-inline bool set_max_radix(HostTables& h, int maxr) {
+inline bool set_max_radix(HostTables& h, int maxr, int maxrz) {
   std::vector<FftPlanD> plans = h.plans;
-  for (FftPlanD& pl : plans) {
+  for (size_t i = 0; i < plans.size(); ++i) {
     std::vector<int> rad;
-    if (!schedule(pl.N, rad, maxr, h.spl)) return false;
-    set_stages(pl, rad);
+    if (!schedule(plans[i].N, rad, h.plan_z[i] ? maxrz : maxr, h.spl)) return false;
+    set_stages(plans[i], rad);
   }
   for (FftPlanD& pl : plans) write_plan_twiddles(h, pl);  // the layout follows the schedule
   h.plans = plans;
   h.maxr = maxr;
+  h.maxrz = maxrz;
   return true;
 }
 
@@ -644,9 +650,9 @@ inline psatd_status build_host(HostTables& h, std::string& err, const int64_t gr
     if (b.P[0] % 2) return bad(PSATD_E_UNSUPPORTED, "padded x length must be even");
     b.H = b.P[0] / 2 + 1;
     b.ld = (b.H % 2) ? b.H : b.H + 1;
-    b.planx = add_plan(h, b.P[0] / 2);
-    b.plany = add_plan(h, b.P[1]);
-    b.planz = add_plan(h, b.P[2]);
+    b.planx = add_plan(h, b.P[0] / 2, false);
+    b.plany = add_plan(h, b.P[1], false);
+    b.planz = add_plan(h, b.P[2], true);
     if (b.planx < 0 || b.plany < 0 || b.planz < 0)
       return bad(PSATD_E_UNSUPPORTED, "no radix schedule of <= 4 stages for a padded length");
     b.twr = add_twiddle(h, b.P[0], twcache);
@@ -741,12 +747,15 @@ inline psatd_status build_host(HostTables& h, std::string& err, const int64_t gr
   // the fewest threads that still keep 16 waves on a CU given how many planes
   // fit its LDS (96^3 FP32: four 40 KB planes x 256 threads; 176^3 FP32: one
   // 127 KB plane x 1024 threads); 512-thread z tiles of 8 pencils; FP64
-  // stages of radix <= 8
+  // x/y stages of radix <= 8 where a plane fits the LDS (radix 16 measured
+  // slower there: 2.41 -> 3.66 ms on 96^3 boxes), radix 16 in the split x/y
+  // passes and the z pass (faster: z pass 2.93 -> 2.59 ms on 96^3 boxes,
+  // 176^3 steps 221-227 -> 215 ms)
   h.ntu = 512;
   h.ntxy = xy_threads_for(h.ldsF);
   build_xy_classes(h);
   build_z_classes(h);
-  if (f64 && !set_max_radix(h, 8)) return bad(PSATD_E_UNSUPPORTED, "no radix-8 schedule");
+  if (f64 && !h.split && !set_max_radix(h, 8, 16)) return bad(PSATD_E_UNSUPPORTED, "no radix-8 schedule");
   return PSATD_OK;
 }
 

@@ -370,6 +370,7 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   // boxes of several tile sizes: one z launch per class (z_pencils 0)
   p->tune[PSATD_TUNE_Z_PENCILS] = h.zcls.empty() ? h.PB : 0;
   p->tune[PSATD_TUNE_MAX_RADIX] = h.maxr;
+  p->tune[PSATD_TUNE_MAX_RADIX_Z] = h.maxrz;
   // boxes of several plane sizes: one x/y launch per class (xy_threads 0)
   p->tune[PSATD_TUNE_XY_THREADS] = h.xyc.size() > 1 ? 0 : h.ntxy;
   p->tune[PSATD_TUNE_Z_THREADS] = h.ntu;
@@ -450,6 +451,7 @@ psatd_status psatd_plan(psatd_plan_t* out, const int64_t grid_n[3], const double
   for (int i = 0; i < d.nxyc; ++i) d.xyc[i] = h.xyc[i];
   d.itemsXYC = reinterpret_cast<const int32_t*>(B + o_xyc);
   d.maxr = h.maxr;
+  d.maxrz = h.maxrz;
   d.xcd = 1;
   d.slab = h.batch_slab;
   d.c = h.c;
@@ -763,11 +765,13 @@ psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
       if (value != 0 && value != 1) return fail(p, PSATD_E_INVALID, "xcd remap must be 0 or 1");
       d.xcd = value;
       break;
-    case PSATD_TUNE_MAX_RADIX: {
+    case PSATD_TUNE_MAX_RADIX:
+    case PSATD_TUNE_MAX_RADIX_Z: {
       if (value != 8 && value != 16) return fail(p, PSATD_E_INVALID, "max radix must be 8 or 16");
       if (value != 16 && p->h.spl) return fail(p, PSATD_E_INVALID, "the matrix-core forms use radix <= 16");
+      const bool zk = key == PSATD_TUNE_MAX_RADIX_Z;
       HostTables trial = p->h;
-      if (!set_max_radix(trial, value))
+      if (!set_max_radix(trial, zk ? p->h.maxr : value, zk ? value : p->h.maxrz))
         return fail(p, PSATD_E_INVALID, "a padded length has no schedule with this max radix");
       HIPCHK(p, hipStreamSynchronize(p->stream));
       HIPCHK(p, hipMemcpy(const_cast<FftPlanD*>(d.plans), trial.plans.data(),
@@ -779,8 +783,10 @@ psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
       p->h.plans = trial.plans;
       p->h.twr = trial.twr;
       p->h.twi = trial.twi;
-      p->h.maxr = value;
-      d.maxr = value;
+      p->h.maxr = trial.maxr;
+      p->h.maxrz = trial.maxrz;
+      d.maxr = trial.maxr;
+      d.maxrz = trial.maxrz;
       break;
     }
     case PSATD_TUNE_XY_THREADS:
@@ -799,7 +805,7 @@ psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
       break;
     default: {
       if (value < 0) return fail(p, PSATD_E_INVALID, "grid size must be >= 0");
-      static const int phase_of[] = {0, 0, kPhaseFwd, kPhaseUpd, kPhaseInv, kPhaseExchEB, 0, 0, 0, 0, 0, 0, 0, 0};
+      static const int phase_of[] = {0, 0, kPhaseFwd, kPhaseUpd, kPhaseInv, kPhaseExchEB, 0, 0, 0, 0, 0, 0, 0, 0, 0};
       d.grid_cap[phase_of[key]] = value;
       if (key == PSATD_TUNE_GRID_EXCH) d.grid_cap[kPhaseExchJ] = value;
     }
@@ -848,17 +854,18 @@ psatd_status psatd_autotune(psatd_plan_t p, void* const E[3], void* const B[3], 
   if (r != PSATD_OK) return r;
   if (steps < 1) return fail(p, PSATD_E_INVALID, "steps_per_trial < 1");
   const std::string key = tune_key(p);
-  static const int keys[] = {PSATD_TUNE_MAX_RADIX, PSATD_TUNE_XY_THREADS, PSATD_TUNE_Z_PENCILS,
-                             PSATD_TUNE_Z_THREADS, PSATD_TUNE_XCD_REMAP};
+  constexpr int nk = 6;
+  static const int keys[nk] = {PSATD_TUNE_MAX_RADIX, PSATD_TUNE_XY_THREADS, PSATD_TUNE_Z_PENCILS,
+                               PSATD_TUNE_Z_THREADS, PSATD_TUNE_XCD_REMAP, PSATD_TUNE_MAX_RADIX_Z};
   if (cache_path) {
     std::ifstream in(cache_path);
     std::string line;
     while (std::getline(in, line)) {
       std::istringstream ls(line);
       std::string k;
-      int v[5];
-      if (!(ls >> k >> v[0] >> v[1] >> v[2] >> v[3] >> v[4]) || k != key) continue;
-      for (int i = 0; i < 5; ++i)
+      int v[nk];
+      if (!(ls >> k >> v[0] >> v[1] >> v[2] >> v[3] >> v[4] >> v[5]) || k != key) continue;
+      for (int i = 0; i < nk; ++i)
         if ((r = psatd_set_tuning(p, keys[i], v[i])) != PSATD_OK) return r;
       if (best_ms) *best_ms = 0.0;
       return PSATD_OK;
@@ -870,16 +877,15 @@ psatd_status psatd_autotune(psatd_plan_t p, void* const E[3], void* const B[3], 
   HIPCHK(p, hipStreamSynchronize(p->stream));
   if (p->h.jmode == PSATD_J_DEPOSITED) HIPCHK(p, launch_sum(p->dp, J, p->stream));
   HIPCHK(p, launch_fill(p->dp, J, 3, p->stream));
-  // Phases are separate kernels: the x/y shape and the z shape are tuned
-  // independently for each largest radix (which both share).
-  double best_total = 1e300;
-  int best[5] = {p->tune[PSATD_TUNE_MAX_RADIX], p->tune[PSATD_TUNE_XY_THREADS], p->tune[PSATD_TUNE_Z_PENCILS],
-                 p->tune[PSATD_TUNE_Z_THREADS], p->tune[PSATD_TUNE_XCD_REMAP]};
+  // Phases are separate kernels with radix limits of their own: the x/y
+  // shape and radix and the z shape and radix are tuned independently.
+  int best[nk] = {p->tune[PSATD_TUNE_MAX_RADIX], p->tune[PSATD_TUNE_XY_THREADS], p->tune[PSATD_TUNE_Z_PENCILS],
+                  p->tune[PSATD_TUNE_Z_THREADS], p->tune[PSATD_TUNE_XCD_REMAP], p->tune[PSATD_TUNE_MAX_RADIX_Z]};
   double ms[kNumPhases];
+  double bxy = 1e300, bz = 1e300, other = 0.0;
   for (int maxr : {16, 8}) {
     if (psatd_set_tuning(p, PSATD_TUNE_MAX_RADIX, maxr) != PSATD_OK) continue;
-    double bxy = 1e300, bz = 1e300, other = 0.0;
-    int cxy = 256, cpb = p->h.PB, czt = 512, cx = 1;
+    if (psatd_set_tuning(p, PSATD_TUNE_MAX_RADIX_Z, maxr) != PSATD_OK) continue;
     for (int xcd : {1, 0}) {
       if ((r = psatd_set_tuning(p, PSATD_TUNE_XCD_REMAP, xcd)) != PSATD_OK) return r;
       for (int xy : {0, 256, 512, 1024}) {
@@ -896,26 +902,28 @@ psatd_status psatd_autotune(psatd_plan_t p, void* const E[3], void* const B[3], 
             if ((r = time_phases(p, E, B, J, steps, ms)) != PSATD_OK) return r;
             const double txy = ms[kPhaseFwd] + ms[kPhaseInv];
             const double tz = ms[kPhaseUpd];
-            if (txy < bxy) { bxy = txy; cxy = xy; cx = xcd; }
-            if (tz < bz) { bz = tz; cpb = pb; czt = zt; }
+            if (txy < bxy) { bxy = txy; best[0] = maxr; best[1] = xy; best[4] = xcd; }
+            if (tz < bz) { bz = tz; best[5] = maxr; best[2] = pb; best[3] = zt; }
             other = ms[kPhaseExchJ] + ms[kPhaseExchEB];
           }
         }
       }
     }
-    const double total = bxy + bz + other;
-    if (total < best_total) {
-      best_total = total;
-      best[0] = maxr; best[1] = cxy; best[2] = cpb; best[3] = czt; best[4] = cx;
-    }
   }
-  for (int i = 0; i < 5; ++i)
+  // the radix limits first (they rebuild the schedules), then the shapes
+  static const int order[nk] = {0, 5, 1, 2, 3, 4};
+  for (int i : order)
     if ((r = psatd_set_tuning(p, keys[i], best[i])) != PSATD_OK) return r;
-  if (best_total >= 1e299) return fail(p, PSATD_E_STATE, "no launch shape could be timed");
+  const double best_total = bxy + bz + other;
+  if (bxy >= 1e299 || bz >= 1e299) return fail(p, PSATD_E_STATE, "no launch shape could be timed");
   if (best_ms) *best_ms = best_total;
   if (cache_path) {
     std::ofstream out(cache_path, std::ios::app);
-    if (out) out << key << " " << best[0] << " " << best[1] << " " << best[2] << " " << best[3] << " " << best[4] << "\n";
+    if (out) {
+      out << key;
+      for (int i = 0; i < nk; ++i) out << " " << best[i];
+      out << "\n";
+    }
   }
   return PSATD_OK;
 }

@@ -287,16 +287,17 @@ hipError_t launch_sum(const DevPlan& p, void* const* J, hipStream_t st) {
   return p.f64 ? sum_t<double>(p, J, st) : sum_t<float>(p, J, st);
 }
 
-// MAXR = 8 kernels exist for the VALU form only.
-#define PSATD_MAXR_SWITCH(SPL, CALL8, CALL16) \
-  do {                                         \
-    if constexpr ((SPL) > 0) {                 \
-      CALL16;                                  \
-    } else if (p.maxr >= 16) {                 \
-      CALL16;                                  \
-    } else {                                   \
-      CALL8;                                   \
-    }                                          \
+// MAXR = 8 kernels exist for the VALU form only.  MR: the pass's largest
+// radix (p.maxr for the x/y passes, p.maxrz for the z passes).
+#define PSATD_MAXR_SWITCH(SPL, MR, CALL8, CALL16) \
+  do {                                             \
+    if constexpr ((SPL) > 0) {                     \
+      CALL16;                                      \
+    } else if ((MR) >= 16) {                       \
+      CALL16;                                      \
+    } else {                                       \
+      CALL8;                                       \
+    }                                              \
   } while (0)
 
 template <typename T, int NT, int MAXR, int SPL>
@@ -312,10 +313,10 @@ static hipError_t xy_shape(const DevPlan& p, int nt, Go go) {
   return with_spl<T>(p.spl, [&](auto sc) -> hipError_t {
     constexpr int SPL = decltype(sc)::value;
     if (nt == 1024)
-      PSATD_MAXR_SWITCH(SPL, return (go.template run<1024, 8, SPL>()), return (go.template run<1024, 16, SPL>()));
+      PSATD_MAXR_SWITCH(SPL, p.maxr, return (go.template run<1024, 8, SPL>()), return (go.template run<1024, 16, SPL>()));
     if (nt == 512)
-      PSATD_MAXR_SWITCH(SPL, return (go.template run<512, 8, SPL>()), return (go.template run<512, 16, SPL>()));
-    PSATD_MAXR_SWITCH(SPL, return (go.template run<256, 8, SPL>()), return (go.template run<256, 16, SPL>()));
+      PSATD_MAXR_SWITCH(SPL, p.maxr, return (go.template run<512, 8, SPL>()), return (go.template run<512, 16, SPL>()));
+    PSATD_MAXR_SWITCH(SPL, p.maxr, return (go.template run<256, 8, SPL>()), return (go.template run<256, 16, SPL>()));
     return hipSuccess;
   });
 }
@@ -399,7 +400,7 @@ static hipError_t upd_t(const DevPlan& p, const Batch& b, void* spec, hipStream_
   auto go = [&](const UpdLaunch& l) -> hipError_t {
     return with_spl<T>(p.spl, [&](auto sc) -> hipError_t {
       constexpr int SPL = decltype(sc)::value;
-      PSATD_MAXR_SWITCH(SPL, return (upd_shape<T, 8, SPL>(p, l, a, st)),
+      PSATD_MAXR_SWITCH(SPL, p.maxrz, return (upd_shape<T, 8, SPL>(p, l, a, st)),
                         return (upd_shape<T, 16, SPL>(p, l, a, st)));
       return hipSuccess;
     });
@@ -530,7 +531,7 @@ static hipError_t heat_z_t(const DevPlan& p, void* spec, double D, double dt, hi
     constexpr int SPL = decltype(sc)::value;
     auto go = [&](auto pbc) -> hipError_t {
       constexpr int PB = decltype(pbc)::value;
-      PSATD_MAXR_SWITCH(SPL,
+      PSATD_MAXR_SWITCH(SPL, p.maxrz,
                         hipLaunchKernelGGL((k_z_heat<T, PB, I, 8, SPL>), dim3(g), dim3(kThreadsXY), p.ldsH, st,
                                            a, p.nU, p.xcd),
                         hipLaunchKernelGGL((k_z_heat<T, PB, I, 16, SPL>), dim3(g), dim3(kThreadsXY), p.ldsH, st,
@@ -570,7 +571,7 @@ static hipError_t x_fwd_t(const DevPlan& p, void* const* in9, void* spec, hipStr
   if (!g) return hipSuccess;
   return with_spl<T>(p.spl, [&](auto sc) -> hipError_t {
     constexpr int SPL = decltype(sc)::value;
-    PSATD_MAXR_SWITCH(SPL,
+    PSATD_MAXR_SWITCH(SPL, p.maxr,
                       hipLaunchKernelGGL((k_x_fwd<T, 8, SPL>), dim3(g), dim3(kThreadsXY), p.ldsX, st, a,
                                          p.nXF, p.xcd),
                       hipLaunchKernelGGL((k_x_fwd<T, 16, SPL>), dim3(g), dim3(kThreadsXY), p.ldsX, st, a,
@@ -589,13 +590,13 @@ static hipError_t y_t(const DevPlan& p, int dir, void* spec, hipStream_t st) {
   return with_spl<T>(p.spl, [&](auto sc) -> hipError_t {
     constexpr int SPL = decltype(sc)::value;
     if (dir < 0)
-      PSATD_MAXR_SWITCH(SPL,
+      PSATD_MAXR_SWITCH(SPL, p.maxr,
                         hipLaunchKernelGGL((k_y<T, -1, 8, SPL>), dim3(g), dim3(kThreadsXY), p.ldsY, st, a, n,
                                            p.xcd),
                         hipLaunchKernelGGL((k_y<T, -1, 16, SPL>), dim3(g), dim3(kThreadsXY), p.ldsY, st, a, n,
                                            p.xcd));
     else
-      PSATD_MAXR_SWITCH(SPL,
+      PSATD_MAXR_SWITCH(SPL, p.maxr,
                         hipLaunchKernelGGL((k_y<T, 1, 8, SPL>), dim3(g), dim3(kThreadsXY), p.ldsY, st, a, n,
                                            p.xcd),
                         hipLaunchKernelGGL((k_y<T, 1, 16, SPL>), dim3(g), dim3(kThreadsXY), p.ldsY, st, a, n,
@@ -616,7 +617,7 @@ static hipError_t x_inv_t(const DevPlan& p, const void* spec, void* const* out6,
     constexpr int SPL = decltype(sc)::value;
     auto go = [&](auto pc) {
       constexpr bool PUSH = decltype(pc)::value;
-      PSATD_MAXR_SWITCH(SPL,
+      PSATD_MAXR_SWITCH(SPL, p.maxr,
                         hipLaunchKernelGGL((k_x_inv<T, I, 8, SPL, PUSH>), dim3(g), dim3(kThreadsXY), p.ldsX, st,
                                            a, p.nXI, p.xcd),
                         hipLaunchKernelGGL((k_x_inv<T, I, 16, SPL, PUSH>), dim3(g), dim3(kThreadsXY), p.ldsX, st,

@@ -52,7 +52,8 @@ struct DevPlan {
   int32_t nxyc;              // x/y launch classes (used when ntxy == 0)
   XyClass xyc[kMaxXyClasses];
   const int32_t* itemsXYC;
-  int32_t maxr;              // largest codelet of the FFT schedules (8 or 16)
+  int32_t maxr;              // largest codelet of the x/y schedules (8 or 16)
+  int32_t maxrz;             // largest codelet of the z schedules
   int32_t xcd;               // 1: consecutive items on the same XCD (L2 sharing)
   int64_t slab;              // complex elements of one spectral field slab
   double c, dt;

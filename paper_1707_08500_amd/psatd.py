@@ -25,7 +25,8 @@ JMODES = {"replicated": J_REPLICATED, "deposited": J_DEPOSITED}
 PHASES = ("exchange_J", "fft_xy_fwd", "z_update", "fft_xy_inv", "exchange_EB")
 TUNING = {"z_pencils": 0, "xcd_remap": 1, "grid_fwd": 2, "grid_upd": 3, "grid_inv": 4,
           "grid_exch": 5, "batch_boxes": 6, "max_radix": 7, "xy_threads": 8, "z_threads": 9,
-          "split_xy": 10, "fuse_eb": 11, "z_reg": 12, "pull_eb": 13}
+          "split_xy": 10, "fuse_eb": 11, "z_reg": 12, "pull_eb": 13,
+          "max_radix_z": 14}
 NPHASES = len(PHASES)
 NOALLOC_SCRATCH_BYTES = 64 << 20  # PSATD_NOALLOC_SCRATCH_BYTES
 

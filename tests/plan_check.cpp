@@ -78,6 +78,8 @@ Dec uniform(const std::string& name, int64_t N0, int64_t N1, int64_t N2, int b0,
   return tiled(name, N, cuts, {gw, gw, gw});
 }
 
+bool t_plan_z_sized(const HostTables& h) { return h.plan_z.size() == h.plans.size(); }
+
 bool check_tables(const Dec& d, const HostTables& h, bool pieces = true) {
   const int nsub = h.nsub;
   // owners of every global cell (brute force)
@@ -260,10 +262,30 @@ int run_case(const Dec& d, int prec, int jmode, int p, bool expect_ok, int& buil
     }
   for (int per : {1, 2, 3, nsub}) set_batches(h, per);
   set_batches(h, 0);
-  for (int r : {8, 16}) {
-    HostTables t = h;
-    (void)set_max_radix(t, r);
-  }
+  // each pass's schedules within its own radix limit (11 always allowed); a
+  // box's x/y and z lengths have plans of their own kind
+  auto radices_ok = [&](const HostTables& t) {
+    for (size_t i = 0; i < t.plans.size(); ++i) {
+      const int lim = t.plan_z[i] ? t.maxrz : t.maxr;
+      int prod = 1;
+      for (int st = 0; st < t.plans[i].nstages; ++st) {
+        const int R = t.plans[i].radix[st];
+        if (R > lim && R != 11) return false;
+        prod *= R;
+      }
+      if (prod != t.plans[i].N) return false;
+    }
+    for (const BoxD& b : t.box)
+      if (t.plan_z[b.planx] || t.plan_z[b.plany] || !t.plan_z[b.planz]) return false;
+    return true;
+  };
+  CHECK(t_plan_z_sized(h) && radices_ok(h), "%s: radix limits", d.name.c_str());
+  for (int r : {8, 16})
+    for (int rz : {8, 16}) {
+      if (h.spl && (r < 16 || rz < 16)) continue;  // matrix-core forms: a radix-16 first stage, refused by the API
+      HostTables t = h;
+      if (set_max_radix(t, r, rz)) CHECK(radices_ok(t), "%s: radix limits %d/%d", d.name.c_str(), r, rz);
+    }
   return 1;
 }
 
