@@ -497,7 +497,8 @@ def test_launch_shapes_do_not_change_results(tmp_path):
     E, B, J = random_fields(N, 12, p=16)
     case = GpuCase(N, lo, n, g, 16, 0.5, 1.0, "f64", "replicated", E, B, J)
     ref = None
-    settings = [dict(), dict(max_radix=8), dict(xy_threads=512), dict(xy_threads=1024), dict(z_threads=1024),
+    settings = [dict(), dict(max_radix=8), dict(max_radix_z=8), dict(max_radix=16, max_radix_z=8),
+                dict(xy_threads=512), dict(xy_threads=1024), dict(z_threads=1024),
                 dict(z_pencils=8), dict(xcd_remap=0), dict(fuse_eb=0), dict(batch_boxes=3),
                 dict(grid_fwd=100, grid_upd=64, grid_inv=96, grid_exch=50), dict(fuse_eb=0, pull_eb=1),
                 dict(max_radix=8, xy_threads=512, z_threads=1024, batch_boxes=2)]
@@ -514,7 +515,7 @@ def test_launch_shapes_do_not_change_results(tmp_path):
             ref = got
         else:
             assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max(), st
-        case.plan.set_tuning(max_radix=16, xy_threads=256, z_threads=512, z_pencils=8,
+        case.plan.set_tuning(max_radix=16, max_radix_z=16, xy_threads=256, z_threads=512, z_pencils=8,
                              xcd_remap=1, batch_boxes=0, grid_fwd=0, grid_upd=0, grid_inv=0,
                              grid_exch=0, fuse_eb=1)
     before = case.plan.tuning()
@@ -530,6 +531,8 @@ def test_launch_shapes_do_not_change_results(tmp_path):
         case.plan.set_tuning(z_pencils=3)
     with pytest.raises(psatd.PsatdError):
         case.plan.set_tuning(xy_threads=300)
+    with pytest.raises(psatd.PsatdError):
+        case.plan.set_tuning(max_radix_z=4)
     assert case.plan.tuning() == before
     # autotuner: times, applies, caches; a second call hits the cache
     cache = str(tmp_path / "psatd_tune.txt")
