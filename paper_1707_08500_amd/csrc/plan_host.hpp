@@ -281,10 +281,14 @@ inline int64_t z_tile_lds(const HostTables& h, int Pz, int PB) {
 
 // Pencils per z tile of one box on its own: 8 (64-byte FP32 / 128-byte FP64
 // rows) where two FP32 tiles (one FP64 tile) of the box fit a compute unit's
-// LDS, else 4; 0 when not even a 4-pencil tile fits.
+// LDS; else, in FP32, 6 where two 6-pencil tiles fit (176-long z: 76 KB
+// each; the z pass of 176^3 boxes 30.3 -> 26.5 ms against 4 pencils, which
+// the 128-VGPR kernel also holds to two tiles per CU); else 4; 0 when not
+// even a 4-pencil tile fits.
 inline int z_pencils_for(const HostTables& h, int Pz) {
   const int64_t t8 = z_tile_lds(h, Pz, 8);
   if ((is_f64(h.prec) ? t8 : 2 * t8) <= kMaxDynLds) return 8;
+  if (!is_f64(h.prec) && 2 * z_tile_lds(h, Pz, 6) <= kMaxDynLds) return 6;
   return z_tile_lds(h, Pz, 4) <= kMaxDynLds ? 4 : 0;
 }
 
@@ -296,14 +300,15 @@ inline void build_z_classes(HostTables& h) {
   h.zcls.clear();
   h.itemsZC.clear();
   std::vector<int> pb(h.nsub);
-  int used = 0;
+  int used = 0;  // bit per tile size: 8, 6, 4
   for (int s = 0; s < h.nsub; ++s) {
     pb[s] = z_pencils_for(h, h.box[s].P[2]);
     if (!pb[s]) return;
-    used |= pb[s] == 8 ? 1 : 2;
+    used |= pb[s] == 8 ? 1 : (pb[s] == 6 ? 2 : 4);
   }
-  if (used != 3) return;
-  for (int PB : {8, 4}) {
+  if (used == 1 || used == 2 || used == 4) return;  // one size: one launch
+  for (int PB : {8, 6, 4}) {
+    if (!(used & (PB == 8 ? 1 : (PB == 6 ? 2 : 4)))) continue;
     ZClass k{};
     k.PB = PB;
     k.U = (int32_t)h.itemsZC.size();
@@ -696,13 +701,16 @@ inline psatd_status build_host(HostTables& h, std::string& err, const int64_t gr
   {
     // 8 pencils (64-byte FP32 / 128-byte FP64 rows): two FP32 96^3 tiles fit a
     // CU's LDS, so one tile's loads overlap the other's transforms.  FP32
-    // tiles of longer z (176: 101 KB) would leave one tile per CU; 4 pencils
-    // keep three (configuration 5 z pass 35.5 -> 30.4 ms).  FP64 keeps 8:
-    // its 4-pencil tiles measured slower on 96^3 boxes.
+    // tiles of longer z (176: 101 KB) would leave one tile per CU; 6 pencils
+    // keep two (z_pencils_for; configuration 5 z pass 35.5 -> 30.4 ms with 4
+    // pencils, 26.5 ms with 6).  FP64 keeps 8: its 4-pencil tiles measured
+    // slower on 96^3 boxes.
     int PB = 8;
     while (PB > 4 && !z_tile_fits(h, maxPz, PB)) PB /= 2;
-    const int64_t tile8 = (int64_t)maxPz * (9 * 8 + 1) * 2 * real_size(precision) + maxPz * 4;
-    if (!f64 && PB == 8 && 2 * tile8 > kMaxDynLds) PB = 4;
+    if (!f64 && PB == 8) {
+      const int own = z_pencils_for(h, maxPz);
+      if (own) PB = own;
+    }
     if (!z_tile_fits(h, maxPz, PB))
       return bad(PSATD_E_UNSUPPORTED, "padded z length too large for the z-update kernel");
     h.PB = PB;

@@ -203,7 +203,9 @@ bool check_tables(const Dec& d, const HostTables& h, bool pieces = true) {
   }
   // z launch classes: every box in exactly one, with all its tiles, within the class's LDS
   if (!h.zcls.empty()) {
-    CHECK(h.zcls.size() == 2, "%s: z class count", d.name.c_str());
+    CHECK(h.zcls.size() >= 2 && h.zcls.size() <= (size_t)kMaxZClasses, "%s: z class count", d.name.c_str());
+    for (size_t c = 1; c < h.zcls.size(); ++c)
+      CHECK(h.zcls[c].PB < h.zcls[c - 1].PB, "%s: z classes by tile size", d.name.c_str());
     for (int s = 0; s < nsub; ++s) {
       int in = 0;
       for (const ZClass& k : h.zcls) {
@@ -218,14 +220,14 @@ bool check_tables(const Dec& d, const HostTables& h, bool pieces = true) {
       }
       CHECK(in == 1, "%s: box %d in %d z classes", d.name.c_str(), s, in);
     }
-    CHECK(h.itemsZC[h.zcls[0].U + nsub] == h.zcls[0].nU && h.itemsZC[h.zcls[1].U + nsub] == h.zcls[1].nU,
-          "%s: z class totals", d.name.c_str());
+    for (const ZClass& k : h.zcls) CHECK(h.itemsZC[k.U + nsub] == k.nU, "%s: z class totals", d.name.c_str());
   }
   return true;
 }
 
 int g_classes = 0;   // built plans with several x/y launch classes
-int g_zclasses = 0;  // built plans with two z launch classes
+int g_zclasses = 0;  // built plans with several z launch classes
+int g_zclasses3 = 0; // ... with three (8, 6 and 4 pencils)
 
 int run_case(const Dec& d, int prec, int jmode, int p, bool expect_ok, int& built) {
   HostTables h;
@@ -252,6 +254,7 @@ int run_case(const Dec& d, int prec, int jmode, int p, bool expect_ok, int& buil
   ++built;
   if (!h.xyc.empty()) ++g_classes;
   if (!h.zcls.empty()) ++g_zclasses;
+  if (h.zcls.size() == 3) ++g_zclasses3;
   if (!check_tables(d, h)) return 0;
   // the launch-shape knobs that rebuild host tables
   const int maxPz = max_padded_z(h);
@@ -316,10 +319,16 @@ int main() {
     ok.push_back(tiled("x/y launch classes", N, cuts, {8, 8, 8, 8, 8, 8}));
   }
   {
-    // padded z lengths of 128 and 160: 8- and 4-pencil FP32 z tiles
+    // padded z lengths of 128 and 160: 8- and 6-pencil FP32 z tiles
     const int64_t N[3] = {32, 32, 256};
     std::vector<int64_t> cuts[3] = {{0, 32}, {0, 32}, {0, 112, 256}};
     ok.push_back(tiled("z launch classes", N, cuts, {8, 8, 8, 8, 8, 8}));
+  }
+  {
+    // padded z lengths of 112, 176 and 240: 8-, 6- and 4-pencil FP32 z tiles
+    const int64_t N[3] = {32, 32, 480};
+    std::vector<int64_t> cuts[3] = {{0, 32}, {0, 32}, {0, 96, 256, 480}};
+    ok.push_back(tiled("three z launch classes", N, cuts, {8, 8, 8, 8, 8, 8}));
   }
   {
     const int64_t N[3] = {20, 21, 15};
@@ -395,7 +404,7 @@ int main() {
       ++g_fail;
     }
   }
-  if (g_fail || built < 30 || passed != built || g_classes == 0 || g_zclasses == 0) {
+  if (g_fail || built < 30 || passed != built || g_classes == 0 || g_zclasses == 0 || g_zclasses3 == 0) {
     std::fprintf(stderr, "plan_check: FAILED (%d failures, %d built, %d passed)\n", g_fail, built, passed);
     return 1;
   }
