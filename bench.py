@@ -434,7 +434,7 @@ def kernel_instance(phase, form, tuning):
         pb = tuning["z_pencils"]
         if pb == 0:  # per-class z launches: every tile size's instance
             return f"psatd::k_z_update<float, *, *, true, {maxr}, {spl}>"
-        nt = 512 if pb in (4, 6) else tuning["z_threads"]
+        nt = 512 if pb in (4, 6, 10) else tuning["z_threads"]
         return f"psatd::k_z_update<float, {nt}, {pb}, true, {maxr}, {spl}>"
     nt = tuning["xy_threads"] or "*"
     if phase == "fft_xy_fwd":

@@ -94,13 +94,12 @@ enum {
 
 /* Launch-shape knobs (psatd_set_tuning).  None changes results beyond rounding order. */
 typedef enum {
-  PSATD_TUNE_Z_PENCILS = 0,  /* (ky,kx) pencils per z-update work-group: 4, 6, 8 or 16 (LDS-limited)
-                                for every subdomain; default 8, or for FP32 plans whose 8-pencil tile of
-                                the longest padded z would leave one tile per compute unit 6 where two
-                                6-pencil tiles fit, else 4.  0 (default for unbatched plans whose
-                                subdomains differ in that respect): one launch per class, 8 pencils where
-                                two FP32 tiles (one FP64 tile) fit a compute unit, else 6 where two FP32
-                                tiles fit, else 4, each with the LDS of its own longest padded z */
+  PSATD_TUNE_Z_PENCILS = 0,  /* (ky,kx) pencils per z-update work-group: 4, 6, 8, 10 or 16
+                                (LDS-limited) for every subdomain.  Default for the longest padded z: FP32
+                                the widest of 10, 8 and 6 of which two tiles fit a compute unit, else 4;
+                                FP64 8, else 4.  0 (default for unbatched plans whose subdomains differ
+                                in that respect): one launch per class of that choice, each with the LDS
+                                of its own longest padded z */
   PSATD_TUNE_XCD_REMAP = 1,  /* 1: consecutive work items on the same XCD (shared L2); 0: dispatch order */
   PSATD_TUNE_GRID_FWD = 2,   /* work-groups of the forward x/y pass: 0 = one per item, else a persistent grid */
   PSATD_TUNE_GRID_UPD = 3,   /* same for the z-update pass */

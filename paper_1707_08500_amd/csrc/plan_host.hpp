@@ -279,16 +279,19 @@ inline int64_t z_tile_lds(const HostTables& h, int Pz, int PB) {
   return (int64_t)Pz * (9 * PB + 1) * (int64_t)(2 * real_size(h.prec)) + (int64_t)Pz * 4;
 }
 
-// Pencils per z tile of one box on its own: 8 (64-byte FP32 / 128-byte FP64
-// rows) where two FP32 tiles (one FP64 tile) of the box fit a compute unit's
-// LDS; else, in FP32, 6 where two 6-pencil tiles fit (176-long z: 76 KB
-// each; the z pass of 176^3 boxes 30.3 -> 26.5 ms against 4 pencils, which
-// the 128-VGPR kernel also holds to two tiles per CU); else 4; 0 when not
-// even a 4-pencil tile fits.
+// Pencils per z tile of one box on its own.  FP32: the widest of 10, 8 and 6
+// pencils of which two tiles fit a compute unit's LDS (the 128-VGPR kernel
+// holds two tiles per CU whatever their width, and wider tiles read longer
+// runs: 96^3 boxes with 10 instead of 8 pencils, step 2.72 -> 2.69 ms;
+// 176^3 boxes with 6 instead of 4, z pass 30.3 -> 26.5 ms), else 4.  FP64: 8
+// where one tile fits, else 4.  0 when not even a 4-pencil tile fits.
 inline int z_pencils_for(const HostTables& h, int Pz) {
-  const int64_t t8 = z_tile_lds(h, Pz, 8);
-  if ((is_f64(h.prec) ? t8 : 2 * t8) <= kMaxDynLds) return 8;
-  if (!is_f64(h.prec) && 2 * z_tile_lds(h, Pz, 6) <= kMaxDynLds) return 6;
+  if (is_f64(h.prec)) {
+    if (z_tile_lds(h, Pz, 8) <= kMaxDynLds) return 8;
+  } else {
+    for (int PB : {10, 8, 6})
+      if (2 * z_tile_lds(h, Pz, PB) <= kMaxDynLds) return PB;
+  }
   return z_tile_lds(h, Pz, 4) <= kMaxDynLds ? 4 : 0;
 }
 
@@ -300,15 +303,15 @@ inline void build_z_classes(HostTables& h) {
   h.zcls.clear();
   h.itemsZC.clear();
   std::vector<int> pb(h.nsub);
-  int used = 0;  // bit per tile size: 8, 6, 4
+  int used = 0;  // bit PB / 2 per tile size
   for (int s = 0; s < h.nsub; ++s) {
     pb[s] = z_pencils_for(h, h.box[s].P[2]);
     if (!pb[s]) return;
-    used |= pb[s] == 8 ? 1 : (pb[s] == 6 ? 2 : 4);
+    used |= 1 << (pb[s] / 2);
   }
-  if (used == 1 || used == 2 || used == 4) return;  // one size: one launch
-  for (int PB : {8, 6, 4}) {
-    if (!(used & (PB == 8 ? 1 : (PB == 6 ? 2 : 4)))) continue;
+  if ((used & (used - 1)) == 0) return;  // one size: one launch
+  for (int PB : {10, 8, 6, 4}) {
+    if (!(used & (1 << (PB / 2)))) continue;
     ZClass k{};
     k.PB = PB;
     k.U = (int32_t)h.itemsZC.size();
@@ -699,12 +702,11 @@ inline psatd_status build_host(HostTables& h, std::string& err, const int64_t gr
     return bad(PSATD_E_UNSUPPORTED, "padded lengths too large for the split x/y passes");
   // z-update tile: PB consecutive (ky, kx) pencils (128-byte rows when possible)
   {
-    // 8 pencils (64-byte FP32 / 128-byte FP64 rows): two FP32 96^3 tiles fit a
-    // CU's LDS, so one tile's loads overlap the other's transforms.  FP32
-    // tiles of longer z (176: 101 KB) would leave one tile per CU; 6 pencils
-    // keep two (z_pencils_for; configuration 5 z pass 35.5 -> 30.4 ms with 4
-    // pencils, 26.5 ms with 6).  FP64 keeps 8: its 4-pencil tiles measured
-    // slower on 96^3 boxes.
+    // Two FP32 tiles per CU, so one tile's loads overlap the other's
+    // transforms, each as wide as two still fit (z_pencils_for: 10 pencils for
+    // 96-long z, 6 for 176; one 8-pencil tile of 176 would fill a CU alone, and
+    // 4 pencils took configuration 5's z pass 35.5 -> 30.4 ms, 6 to 26.5 ms).
+    // FP64 keeps 8: its 4-pencil tiles measured slower on 96^3 boxes.
     int PB = 8;
     while (PB > 4 && !z_tile_fits(h, maxPz, PB)) PB /= 2;
     if (!f64 && PB == 8) {

@@ -685,7 +685,7 @@ psatd_status psatd_set_tuning(psatd_plan_t p, int32_t key, int32_t value) {
         d.zcl = 1;
         break;
       }
-      if (value != 4 && value != 6 && value != 8 && value != 16)
+      if (value != 4 && value != 6 && value != 8 && value != 10 && value != 16)
         return fail(p, PSATD_E_INVALID, "z pencils must be 0 (per launch class), 4, 6, 8 or 16");
       if (!z_tile_fits(p->h, max_padded_z(p->h), value))
         return fail(p, PSATD_E_INVALID, "z tile does not fit the LDS");
@@ -894,7 +894,7 @@ psatd_status psatd_autotune(psatd_plan_t p, void* const E[3], void* const B[3], 
         // 0: one launch per class of plane size, for uneven boxes of an unbatched plan
         if (xy == 0 && (p->h.xyc.size() < 2 || p->h.batches.size() > 1)) continue;
         if ((r = psatd_set_tuning(p, PSATD_TUNE_XY_THREADS, xy)) != PSATD_OK) return r;
-        for (int pb : {0, 16, 8, 6, 4}) {  // 0: per class of tile size, when the plan has classes
+        for (int pb : {0, 16, 10, 8, 6, 4}) {  // 0: per class of tile size, when the plan has classes
           if (psatd_set_tuning(p, PSATD_TUNE_Z_PENCILS, pb) != PSATD_OK) continue;
           for (int zt : {512, 1024}) {
             if ((r = psatd_set_tuning(p, PSATD_TUNE_Z_THREADS, zt)) != PSATD_OK) return r;

@@ -96,14 +96,14 @@ struct XyClass {
 constexpr int kMaxXyClasses = 3;
 
 // A launch class of the z pass: the boxes whose z tile takes the same number
-// of pencils (8 where two such tiles of the box fit a compute unit's LDS in
-// FP32, or one in FP64; else 6 where two FP32 tiles of 6 fit; else 4),
-// launched with the LDS of the class's longest padded z.  Work list: a prefix
-// over all boxes at offset U of one table.
+// of pencils (FP32: the widest of 10, 8, 6 of which two tiles fit a compute
+// unit's LDS, else 4; FP64: 8 where one tile fits, else 4), launched with the
+// LDS of the class's longest padded z.  Work list: a prefix over all boxes at
+// offset U of one table.
 struct ZClass {
   int32_t PB, lds, U, nU;
 };
-constexpr int kMaxZClasses = 3;
+constexpr int kMaxZClasses = 4;
 
 // Pencils per work-group of the register z pass (9 fields share its lanes).
 constexpr int zreg_pencils(int L, int W) { return (64 * W / L) / 9; }

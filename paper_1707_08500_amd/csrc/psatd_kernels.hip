@@ -218,7 +218,8 @@ static hipError_t prepare_t(int ldsF, int ldsI, int ldsU, int ldsX, int ldsY) {
                        (const void*)k_z_update<T, 1024, 8, I, MAXR, SPL>,
                        (const void*)k_z_update<T, 1024, 16, I, MAXR, SPL>,
                        (const void*)k_z_update<T, 512, 4, I, MAXR, SPL>,
-                       (const void*)k_z_update<T, 512, 6, I, MAXR, SPL>};
+                       (const void*)k_z_update<T, 512, 6, I, MAXR, SPL>,
+                       (const void*)k_z_update<T, 512, 10, I, MAXR, SPL>};
   hipError_t e;
   for (const void* f : xy)
     if (ldsF <= kMaxDynLds && (e = set_lds(f, ldsF)) != hipSuccess) return e;
@@ -227,7 +228,8 @@ static hipError_t prepare_t(int ldsF, int ldsI, int ldsU, int ldsX, int ldsY) {
   for (const void* f : upd)
     if ((e = set_lds(f, ldsU)) != hipSuccess) return e;
   const void* heat[] = {(const void*)k_z_heat<T, 4, I, MAXR, SPL>, (const void*)k_z_heat<T, 6, I, MAXR, SPL>,
-                        (const void*)k_z_heat<T, 8, I, MAXR, SPL>, (const void*)k_z_heat<T, 16, I, MAXR, SPL>};
+                        (const void*)k_z_heat<T, 8, I, MAXR, SPL>, (const void*)k_z_heat<T, 10, I, MAXR, SPL>,
+                        (const void*)k_z_heat<T, 16, I, MAXR, SPL>};
   for (const void* f : heat)
     if ((e = set_lds(f, ldsU)) != hipSuccess) return e;
   if ((e = set_lds((const void*)k_x_fwd<T, MAXR, SPL>, ldsX)) != hipSuccess) return e;
@@ -383,6 +385,7 @@ template <typename T, int MAXR, int SPL>
 static hipError_t upd_shape(const DevPlan& p, const UpdLaunch& l, const UpdArgs<T>& a, hipStream_t st) {
   if (l.PB == 4) return upd_launch<T, 512, 4, MAXR, SPL>(p, l, a, st);
   if (l.PB == 6) return upd_launch<T, 512, 6, MAXR, SPL>(p, l, a, st);
+  if (l.PB == 10) return upd_launch<T, 512, 10, MAXR, SPL>(p, l, a, st);
   if (p.ntu == 1024)
     return l.PB == 16 ? upd_launch<T, 1024, 16, MAXR, SPL>(p, l, a, st)
                       : upd_launch<T, 1024, 8, MAXR, SPL>(p, l, a, st);
@@ -542,6 +545,7 @@ static hipError_t heat_z_t(const DevPlan& p, void* spec, double D, double dt, hi
     };
     if (p.PB == 4) return go(std::integral_constant<int, 4>{});
     if (p.PB == 6) return go(std::integral_constant<int, 6>{});
+    if (p.PB == 10) return go(std::integral_constant<int, 10>{});
     if (p.PB == 8) return go(std::integral_constant<int, 8>{});
     return go(std::integral_constant<int, 16>{});
   });

@@ -227,7 +227,7 @@ bool check_tables(const Dec& d, const HostTables& h, bool pieces = true) {
 
 int g_classes = 0;   // built plans with several x/y launch classes
 int g_zclasses = 0;  // built plans with several z launch classes
-int g_zclasses3 = 0; // ... with three (8, 6 and 4 pencils)
+int g_zclasses3 = 0; // ... with four (10, 8, 6 and 4 pencils)
 
 int run_case(const Dec& d, int prec, int jmode, int p, bool expect_ok, int& built) {
   HostTables h;
@@ -254,7 +254,7 @@ int run_case(const Dec& d, int prec, int jmode, int p, bool expect_ok, int& buil
   ++built;
   if (!h.xyc.empty()) ++g_classes;
   if (!h.zcls.empty()) ++g_zclasses;
-  if (h.zcls.size() == 3) ++g_zclasses3;
+  if (h.zcls.size() == 4) ++g_zclasses3;
   if (!check_tables(d, h)) return 0;
   // the launch-shape knobs that rebuild host tables
   const int maxPz = max_padded_z(h);
@@ -319,16 +319,16 @@ int main() {
     ok.push_back(tiled("x/y launch classes", N, cuts, {8, 8, 8, 8, 8, 8}));
   }
   {
-    // padded z lengths of 128 and 160: 8- and 6-pencil FP32 z tiles
+    // padded z lengths of 128 and 160: 8- and 6-pencil FP32 z tiles (FP64 8 and 4)
     const int64_t N[3] = {32, 32, 256};
     std::vector<int64_t> cuts[3] = {{0, 32}, {0, 32}, {0, 112, 256}};
     ok.push_back(tiled("z launch classes", N, cuts, {8, 8, 8, 8, 8, 8}));
   }
   {
-    // padded z lengths of 112, 176 and 240: 8-, 6- and 4-pencil FP32 z tiles
-    const int64_t N[3] = {32, 32, 480};
-    std::vector<int64_t> cuts[3] = {{0, 32}, {0, 32}, {0, 96, 256, 480}};
-    ok.push_back(tiled("three z launch classes", N, cuts, {8, 8, 8, 8, 8, 8}));
+    // padded z lengths of 80, 112, 176 and 240: 10-, 8-, 6- and 4-pencil FP32 z tiles
+    const int64_t N[3] = {32, 32, 544};
+    std::vector<int64_t> cuts[3] = {{0, 32}, {0, 32}, {0, 64, 160, 320, 544}};
+    ok.push_back(tiled("four z launch classes", N, cuts, {8, 8, 8, 8, 8, 8}));
   }
   {
     const int64_t N[3] = {20, 21, 15};

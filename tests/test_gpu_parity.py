@@ -499,7 +499,7 @@ def test_launch_shapes_do_not_change_results(tmp_path):
     ref = None
     settings = [dict(), dict(max_radix=8), dict(max_radix_z=8), dict(max_radix=16, max_radix_z=8),
                 dict(xy_threads=512), dict(xy_threads=1024), dict(z_threads=1024),
-                dict(z_pencils=8), dict(z_pencils=6), dict(z_pencils=4), dict(xcd_remap=0), dict(fuse_eb=0), dict(batch_boxes=3),
+                dict(z_pencils=10), dict(z_pencils=8), dict(z_pencils=6), dict(z_pencils=4), dict(xcd_remap=0), dict(fuse_eb=0), dict(batch_boxes=3),
                 dict(grid_fwd=100, grid_upd=64, grid_inv=96, grid_exch=50), dict(fuse_eb=0, pull_eb=1),
                 dict(max_radix=8, xy_threads=512, z_threads=1024, batch_boxes=2)]
     for st in settings:
@@ -791,17 +791,17 @@ def test_xy_launch_classes(precision, tol):
 Z_CLASS_LAYOUTS = {
     # padded z 128 and 160: FP32 tiles of 8 and 6 pencils, FP64 8 and 4
     "two": ((32, 32, 256), [[0, 0, 0], [0, 0, 112]], [[32, 32, 112], [32, 32, 144]]),
-    # padded z 112, 176 and 240: FP32 tiles of 8, 6 and 4 pencils, FP64 8 and 4
-    "three": ((32, 32, 480), [[0, 0, 0], [0, 0, 96], [0, 0, 256]],
-              [[32, 32, 96], [32, 32, 160], [32, 32, 224]]),
+    # padded z 80, 112, 176 and 240: FP32 tiles of 10, 8, 6 and 4 pencils, FP64 8 and 4
+    "four": ((32, 32, 544), [[0, 0, 0], [0, 0, 64], [0, 0, 160], [0, 0, 320]],
+             [[32, 32, 64], [32, 32, 96], [32, 32, 160], [32, 32, 224]]),
 }
 
 
 @pytest.mark.parametrize("layout", sorted(Z_CLASS_LAYOUTS))
 @pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 1e-5)])
 def test_z_launch_classes(precision, tol, layout):
-    """Subdomains whose padded z lengths take different z tiles (8 pencils
-    where two FP32 tiles fit a CU, else 6 where two fit, else 4) run the z
+    """Subdomains whose padded z lengths take different z tiles (FP32: the
+    widest of 10, 8, 6 pencils of which two tiles fit a CU, else 4) run the z
     pass as one launch per class (the default, z_pencils 0): the step matches
     the oracle (Sec. 3.2, Fig. 3 with the update of Sec. 3.1) and is
     byte-identical to one launch of every box with 4-pencil tiles; the knob
